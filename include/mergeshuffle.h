@@ -1,0 +1,151 @@
+/*
+ * mergeshuffle.h -- C ABI of the MI355X (gfx950) MergeShuffle library.
+ *
+ * MergeShuffle (Bacher, Bodini, Hollender, Lumbroso, arXiv 1508.03167) draws a
+ * uniformly random permutation of an array: the array is cut into q = 2^c
+ * blocks [n*i/q, n*(i+1)/q), c the least level count with (n >> c) <= cutoff
+ * (Algorithm MergeShuffle; shuffle() listing in Appendix A.2); each block is
+ * shuffled with Fisher-Yates (Algorithm 1); then for levels L = 1..c each
+ * pair of adjacent shuffled blocks is merged by Merge (Algorithm 2, Section
+ * 1.1; merge() listing in Appendix A.1): coin flips interleave the two halves
+ * until a flip falls on an exhausted half, and the remaining slots are placed
+ * by Fisher-Yates insertion.  Lemma 1 shows the result is uniform.
+ *
+ * Result contract.  Every entry point computes out[t] = in[pi(t)], where pi is
+ * the permutation MergeShuffle(n, cutoff, seed) produces under this library's
+ * bit source:
+ *   - coin flip t of merge m at level L: bit (t & 31) of word (t >> 5) & 3 of
+ *     Philox-4x32-10(counter = (t >> 7, m, L, 1 << 28), key = (lo32(seed),
+ *     hi32(seed)));
+ *   - the d-th bounded draw of unit u (leaf block u at level 0, merge u at
+ *     level L >= 1) is a Fast Dice Roller draw [Lumbroso13] whose bits are read
+ *     most-significant first from word d & 3 of Philox(d >> 2, u, L, 2 << 28),
+ *     then from Philox(d, u, L, (3 << 28) | j), j = 0, 1, ..., words 0..3;
+ *   - the coin-flip loop places elements as a stable interleave: output slot
+ *     a+b takes A[a] on a 0 flip and B[b] on a 1 flip.
+ * pi depends only on (n, cutoff, seed): not on element values, element size,
+ * stream, launch shape or batching.
+ *
+ * Random bits.  The optional device counter d_bits of the _ex entry points is
+ * incremented by the number of fair bits the call consumed: P+1 flips per
+ * merge (P = slots filled by the coin-flip loop, including the flip that ends
+ * it) plus every bit read by the bounded draws -- the cost Lemma 2 and the
+ * paper's bit-count table measure.
+ *
+ * Memory and ownership.  Data pointers are device pointers owned by the
+ * caller, aligned to the element size; elements are 4, 8 or 16 bytes; arrays
+ * hold n < 2^32 - 2^16 elements.  The library owns per-(device, stream)
+ * scratch: one array of n * elem_bytes bytes (the HBM merge levels run
+ * out of place between the caller's array and this scratch) and the merge
+ * plan (about n/64 bytes plus the tail tables).  Scratch is allocated on first
+ * use and grown (after synchronizing that stream) when a larger call needs it;
+ * ms_release() frees it.
+ *
+ * Asynchrony and errors.  Calls validate their arguments, make the scratch,
+ * enqueue kernels on `stream` (a hipStream_t; NULL = the default stream) and
+ * return.  Argument, allocation and launch errors are returned at once as a
+ * negative status; ms_last_error() gives the calling thread's last message.
+ * Kernel faults surface at the caller's next synchronization.  The merge plan
+ * keeps the insertion-loop tables of every level in capacity-bounded pools
+ * sized far above the expected need (the chance that a call exceeds them is
+ * below 2^-60); if one ever overflows the call's output is wrong and a flag
+ * is set that ms_device_status() reports.  Calls on different streams may run
+ * concurrently; calls on one stream run in order.
+ */
+#ifndef MERGESHUFFLE_H
+#define MERGESHUFFLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MS_OK = 0,
+  MS_ERR_INVALID = -1,     /* null pointer with n > 0, misaligned pointer, bad cutoff */
+  MS_ERR_UNSUPPORTED = -2, /* element size not 4/8/16, n too large, leaf too large */
+  MS_ERR_NOMEM = -3,       /* scratch allocation failed */
+  MS_ERR_HIP = -4,         /* a HIP runtime call failed (no device, launch error) */
+  MS_ERR_CAPACITY = -5     /* ms_device_status: a plan pool overflowed */
+};
+
+/* Knobs of the _ex entry points; a NULL config means all defaults.
+ * leaf_B changes the permutation (it is the paper's cutoff); the others never do. */
+typedef struct ms_config {
+  uint32_t leaf_B;          /* cutoff: leaves hold at most leaf_B+1 elements; 0 = 4096; at most 4096 */
+  uint32_t levels_per_pass; /* HBM merge levels fused per pass; 0 = default; clamped to the
+                               supported maximum (currently 1) */
+  uint32_t lds_levels_max;  /* cap on merge levels run in LDS by the leaf kernel; 0 = as many as fit */
+  uint32_t flags;           /* MS_CFG_HBM_ONLY: run every merge level as an HBM pass */
+} ms_config;
+
+#define MS_CFG_HBM_ONLY 1u
+
+/* Shuffle n elements of elem_bytes bytes at dev_ptr in place (Algorithm
+ * MergeShuffle with cutoff 4096), seed as above, on stream. */
+int ms_shuffle(void* dev_ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed, void* stream);
+
+/* Write the random permutation of 0..n-1 to the device array out (uint32),
+ * i.e. ms_shuffle of the identity, generating the identity in the leaf kernel
+ * instead of reading it.  Default stream. */
+int ms_permutation(uint32_t* out, uint64_t n, uint64_t seed);
+
+/* Shuffle `count` independent uint32 device arrays ptrs[a] of sizes[a]
+ * elements (host arrays of pointers and sizes), array a with seed + a.
+ * Arrays must not overlap. */
+int ms_shuffle_batched(void* const* ptrs, const uint64_t* sizes, uint32_t count, uint64_t seed, void* stream);
+
+/* As above with explicit knobs and an optional device counter (+= bits). */
+int ms_shuffle_ex(void* dev_ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed, void* stream,
+                  const ms_config* cfg, unsigned long long* d_bits);
+int ms_permutation_ex(uint32_t* out, uint64_t n, uint64_t seed, void* stream, const ms_config* cfg,
+                      unsigned long long* d_bits);
+/* elem_bytes: host array of per-array element sizes, or NULL for all-uint32;
+ * d_bits_per_array: device array of count counters, or NULL. */
+int ms_shuffle_batched_ex(void* const* ptrs, const uint64_t* sizes, const uint32_t* elem_bytes, uint32_t count,
+                          uint64_t seed, void* stream, const ms_config* cfg, unsigned long long* d_bits_per_array);
+
+/* Plan of one call, computed on the host (no GPU needed). */
+typedef struct ms_plan_info {
+  uint32_t levels;        /* c */
+  uint32_t lds_levels;    /* merge levels done inside the leaf kernel */
+  uint32_t hbm_levels;    /* merge levels done as HBM passes */
+  uint32_t leaf_B;        /* cutoff used */
+  uint64_t leaves;        /* q = 2^c */
+  uint64_t scratch_bytes; /* library scratch for this call (array copy + plan) */
+  uint64_t pass_tiles;    /* workgroups of one HBM merge pass */
+} ms_plan_info;
+
+int ms_plan(uint64_t n, uint32_t elem_bytes, const ms_config* cfg, ms_plan_info* out);
+
+/* Library scratch a call of this size needs, in bytes (0 if unsupported). */
+uint64_t ms_scratch_bytes(uint64_t n, uint32_t elem_bytes);
+
+/* The cutoff the library uses for a call of this size (for replaying a call
+ * on another implementation). */
+uint32_t ms_leaf_B_for(uint64_t n, uint32_t elem_bytes);
+
+/* Synchronize `stream`, then read and clear the device status flags of the
+ * current device (bit 0: target pool overflow, bit 1: tail pool overflow).
+ * Returns MS_OK if clear, MS_ERR_CAPACITY if a flag was set. */
+int ms_device_status(void* stream, uint32_t* flags);
+
+/* Free every scratch buffer of the current device (synchronizes it). */
+int ms_release(void);
+
+/* The calling thread's last error message ("" if none). */
+const char* ms_last_error(void);
+
+/* Kernel timing: while enabled, each kernel class launched by the library is
+ * bracketed by HIP events on the call's stream.  Classes: 0 plan, 1 leaf,
+ * 2 merge pass, 3 patch.  ms_profile_read synchronizes the recorded events,
+ * writes total milliseconds and launch counts per class, and clears them. */
+int ms_profile_enable(int on);
+int ms_profile_read(double ms_per_class[4], uint64_t launches_per_class[4]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MERGESHUFFLE_H */

@@ -1,0 +1,501 @@
+// ms_api.hip -- host runtime and C ABI of the MergeShuffle library.
+//
+// The planner turns (n, element size, cutoff) into the level layout of the
+// driver (shuffle() listing, Appendix A.2): c levels over q = 2^c leaves, the
+// first `lds_levels` merge levels fused into the leaf kernel, the rest as HBM
+// passes with their data-independent plan.  Scratch (one array copy for the
+// out-of-place HBM levels plus the plan tables) is kept per (device, stream)
+// and grown on demand; every launch is enqueued on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mergeshuffle.h"
+#include "ms_plan.hpp"
+
+namespace ms {
+struct LeafArgs {
+  const void* in;
+  void* out;
+  uint64_t n;
+  uint32_t c;
+  uint32_t lds_levels;
+  uint32_t key0, key1;
+  unsigned long long* bits;
+};
+struct PassArgs {
+  const void* in;
+  void* out;
+  uint64_t n;
+  uint32_t c, L, tpm, cpm;
+  uint64_t chunk_base;
+  uint64_t merge_base;
+  const uint16_t* zloc;
+  const uint32_t* zc;
+  const uint32_t* P;
+  const uint8_t* side;
+  uint32_t key0, key1;
+};
+void launch_plan(const PlanArgs& pa, hipStream_t st);
+void launch_leaf(const LeafArgs& a, uint32_t eb, bool ident, uint64_t grid, hipStream_t st);
+void launch_merge_pass(const PassArgs& a, uint32_t eb, uint64_t grid, hipStream_t st);
+void launch_patch(const PlanArgs& pa, int l, const void* in, void* out, uint32_t eb, hipStream_t st);
+int leaf_capacity(uint32_t eb);
+int leaf_max_block();
+int leaf_max_levels();
+int pass_tile(uint32_t eb);
+}  // namespace ms
+
+namespace {
+
+using namespace ms;
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(MS_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr uint64_t kMaxN = (1ull << 32) - (1ull << 16);
+constexpr uint32_t kDefaultB = 4096;
+
+// ---------------------------------------------------------------------------
+// planner
+// ---------------------------------------------------------------------------
+struct Layout {
+  size_t zloc, ctot, zc, P, side, kcnt, toff, tail_src, bcnt, bfill, boff, part, pool_x, pool_step, pool_src;
+  size_t bytes;
+};
+
+struct HostPlan {
+  uint64_t n = 0;
+  uint32_t eb = 4, B = kDefaultB, c = 0, lam = 0, nlev = 0;
+  uint64_t q = 1;
+  uint64_t pass_tiles = 0;
+  PlanArgs pa;
+  Layout lay;
+};
+
+uint64_t ceil_shift(uint64_t n, uint32_t s) { return (n + (1ull << s) - 1) >> s; }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
+  if (eb != 4 && eb != 8 && eb != 16) return fail(MS_ERR_UNSUPPORTED, "element size %u not in {4,8,16}", eb);
+  if (n > kMaxN) return fail(MS_ERR_UNSUPPORTED, "n = %llu exceeds %llu", (unsigned long long)n,
+                             (unsigned long long)kMaxN);
+  uint32_t B = cfg && cfg->leaf_B ? cfg->leaf_B : kDefaultB;
+  if (B + 1 > (uint32_t)leaf_max_block()) return fail(MS_ERR_UNSUPPORTED, "cutoff %u above %d", B, leaf_max_block() - 1);
+  memset(&hp.pa, 0, sizeof hp.pa);
+  hp.n = n;
+  hp.eb = eb;
+  hp.B = B;
+  uint32_t c = 0;
+  while ((n >> c) > B) ++c;
+  hp.c = c;
+  hp.q = 1ull << c;
+  const uint64_t scap = (uint64_t)leaf_capacity(eb);
+  if (ceil_shift(n, c) > scap) return fail(MS_ERR_UNSUPPORTED, "leaf of %llu elements does not fit in LDS",
+                                           (unsigned long long)ceil_shift(n, c));
+  uint32_t lam_max = (uint32_t)leaf_max_levels();
+  if (cfg && cfg->lds_levels_max && cfg->lds_levels_max < lam_max) lam_max = cfg->lds_levels_max;
+  if (cfg && (cfg->flags & MS_CFG_HBM_ONLY)) lam_max = 0;  // every merge level as an HBM pass
+  uint32_t lam = 0;
+  while (lam < c && lam < lam_max && ceil_shift(n, c - lam - 1) <= scap) ++lam;
+  hp.lam = lam;
+  hp.nlev = c - lam;
+  PlanArgs& pa = hp.pa;
+  pa.n = n;
+  pa.c = c;
+  pa.lds_levels = lam;
+  pa.nlev = hp.nlev;
+  const uint32_t T = (uint32_t)pass_tile(eb);
+  uint64_t chunks = 0, merges = 0, buckets = 0, wgs = 0, cap = 0, tiles = 0;
+  for (uint32_t l = 0; l < hp.nlev; ++l) {
+    HbmLevel& lv = pa.lev[l];
+    const uint32_t L = lam + 1 + l;
+    lv.L = L;
+    lv.nmerge = (uint32_t)(hp.q >> L);
+    const uint64_t nmax = ceil_shift(n, c - L);
+    lv.nmax = (uint32_t)nmax;
+    lv.cpm = (uint32_t)ceil_shift(nmax + 1, kChunkLog);
+    lv.bpm = (uint32_t)ceil_shift(nmax, kBucketLog);
+    lv.tpm = (uint32_t)((nmax + T - 1) / T);
+    const double ek = 0.8 * std::sqrt((double)nmax);
+    lv.wpm = (uint32_t)std::max(1.0, std::ceil(ek / 1024.0));
+    lv.chunk_base = chunks;
+    lv.merge_base = merges;
+    lv.bucket_base = buckets;
+    lv.wg_base = wgs;
+    // insertion-loop steps of this level: about 0.8 sqrt(N) per merge; the
+    // bound adds 0.4 sqrt(N) per merge and 14 sqrt(n) for the whole level
+    double bnd = 1.2 * (double)lv.nmerge * std::sqrt((double)nmax) + 14.0 * std::sqrt((double)n) + 64.0;
+    uint64_t lcap = (uint64_t)std::ceil(bnd);
+    if (lcap > n) lcap = n;
+    lv.pool_cap = lcap;
+    chunks += (uint64_t)lv.nmerge * lv.cpm;
+    merges += lv.nmerge;
+    buckets += (uint64_t)lv.nmerge * lv.bpm;
+    wgs += (uint64_t)lv.nmerge * lv.wpm;
+    cap += lcap;
+    tiles = std::max<uint64_t>(tiles, (uint64_t)lv.nmerge * lv.tpm);
+  }
+  pa.total_chunks = chunks;
+  pa.total_merges = merges;
+  pa.total_buckets = buckets;
+  pa.total_tail_wgs = wgs;
+  pa.pool_cap = cap;
+  pa.tail_cap = cap;
+  hp.pass_tiles = tiles;
+  Layout& y = hp.lay;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+  y.zloc = take(chunks * 256 * 2);
+  y.ctot = take(chunks * 4);
+  y.zc = take(chunks * 4);
+  y.P = take(merges * 4);
+  y.side = take(merges);
+  y.kcnt = take(merges * 4);
+  y.toff = take((merges + 1) * 4);
+  y.tail_src = take(cap * 4);
+  y.bcnt = take(buckets * 4);
+  y.bfill = take(buckets * 4);
+  y.boff = take((buckets + 1) * 4);
+  y.part = take(((std::max(buckets, merges) + 2047) / 2048 + 1) * 4);
+  y.pool_x = take(cap * 4);
+  y.pool_step = take(cap * 4);
+  y.pool_src = take(cap * 4);
+  y.bytes = hp.nlev ? o : 0;
+  return MS_OK;
+}
+
+uint64_t scratch_of(const HostPlan& hp) { return (hp.nlev ? hp.n * hp.eb : 0) + hp.lay.bytes; }
+
+// ---------------------------------------------------------------------------
+// per-device context and per-stream scratch
+// ---------------------------------------------------------------------------
+struct Arena {
+  void* data = nullptr;   // array copy
+  size_t data_bytes = 0;
+  void* plan = nullptr;   // plan tables
+  size_t plan_bytes = 0;
+};
+
+struct DeviceCtx {
+  bool init = false;
+  uint32_t* status = nullptr;
+  unsigned long long* dummy_bits = nullptr;
+  std::map<hipStream_t, Arena> arenas;
+};
+
+std::mutex g_mu;
+DeviceCtx g_dev[64];
+
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+};
+bool g_prof = false;
+std::vector<ProfRec> g_prof_recs;
+
+int device_ctx(DeviceCtx** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(MS_ERR_HIP, "device %d out of range", dev);
+  DeviceCtx& d = g_dev[dev];
+  if (!d.init) {
+    HIP_TRY(hipMalloc(&d.status, 256));
+    HIP_TRY(hipMemset(d.status, 0, 256));
+    d.dummy_bits = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(d.status) + 64);
+    d.init = true;
+  }
+  *out = &d;
+  return MS_OK;
+}
+
+int ensure(void** p, size_t* have, size_t need, hipStream_t st) {
+  if (need <= *have) return MS_OK;
+  if (*p) {
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipFree(*p));
+    *p = nullptr;
+    *have = 0;
+  }
+  if (getenv("MS_FAIL_ALLOC")) return fail(MS_ERR_NOMEM, "scratch allocation of %zu bytes refused (MS_FAIL_ALLOC)", need);
+  hipError_t e = hipMalloc(p, need);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(MS_ERR_NOMEM, "hipMalloc(%zu): %s", need, hipGetErrorString(e));
+  }
+  *have = need;
+  return MS_OK;
+}
+
+struct ProfScope {
+  int cls;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(int c, hipStream_t s) : cls(c), st(s) {
+    if (!g_prof) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+    (void)hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    (void)hipEventRecord(b, st);
+    g_prof_recs.push_back({cls, a, b});
+  }
+};
+
+int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, const ms_config* cfg,
+            unsigned long long* d_bits, bool ident) {
+  HostPlan hp;
+  int rc = make_plan(n, eb, cfg, hp);
+  if (rc) return rc;
+  if (n > 0 && ptr == nullptr) return fail(MS_ERR_INVALID, "null pointer with n = %llu", (unsigned long long)n);
+  if (((uintptr_t)ptr) % eb != 0) return fail(MS_ERR_INVALID, "pointer not aligned to %u bytes", eb);
+  if (n <= 1) return MS_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx* dc;
+  if ((rc = device_ctx(&dc))) return rc;
+  Arena& ar = dc->arenas[st];
+  if ((rc = ensure(&ar.data, &ar.data_bytes, hp.nlev ? n * eb : 0, st))) return rc;
+  if ((rc = ensure(&ar.plan, &ar.plan_bytes, hp.lay.bytes, st))) return rc;
+  unsigned long long* bits = d_bits ? d_bits : dc->dummy_bits;
+  PlanArgs& pa = hp.pa;
+  pa.key0 = (uint32_t)seed;
+  pa.key1 = (uint32_t)(seed >> 32);
+  pa.bits = bits;
+  pa.status = dc->status;
+  if (hp.nlev) {
+    char* b = reinterpret_cast<char*>(ar.plan);
+    const Layout& y = hp.lay;
+    pa.zloc = reinterpret_cast<uint16_t*>(b + y.zloc);
+    pa.ctot = reinterpret_cast<uint32_t*>(b + y.ctot);
+    pa.zc = reinterpret_cast<uint32_t*>(b + y.zc);
+    pa.P = reinterpret_cast<uint32_t*>(b + y.P);
+    pa.side = reinterpret_cast<uint8_t*>(b + y.side);
+    pa.kcnt = reinterpret_cast<uint32_t*>(b + y.kcnt);
+    pa.toff = reinterpret_cast<uint32_t*>(b + y.toff);
+    pa.tail_src = reinterpret_cast<uint32_t*>(b + y.tail_src);
+    pa.bcnt = reinterpret_cast<uint32_t*>(b + y.bcnt);
+    pa.bfill = reinterpret_cast<uint32_t*>(b + y.bfill);
+    pa.boff = reinterpret_cast<uint32_t*>(b + y.boff);
+    pa.part = reinterpret_cast<uint32_t*>(b + y.part);
+    pa.pool_x = reinterpret_cast<uint32_t*>(b + y.pool_x);
+    pa.pool_step = reinterpret_cast<uint32_t*>(b + y.pool_step);
+    pa.pool_src = reinterpret_cast<uint32_t*>(b + y.pool_src);
+    ProfScope ps(0, st);
+    launch_plan(pa, st);
+  }
+  void* X = ptr;
+  void* Y = ar.data;
+  void* cur = (hp.nlev % 2 == 0) ? X : Y;
+  {
+    LeafArgs la;
+    la.in = X;
+    la.out = cur;
+    la.n = n;
+    la.c = hp.c;
+    la.lds_levels = hp.lam;
+    la.key0 = pa.key0;
+    la.key1 = pa.key1;
+    la.bits = bits;
+    ProfScope ps(1, st);
+    launch_leaf(la, eb, ident, hp.q >> hp.lam, st);
+  }
+  for (uint32_t l = 0; l < hp.nlev; ++l) {
+    void* other = cur == X ? Y : X;
+    const HbmLevel& lv = pa.lev[l];
+    PassArgs a;
+    a.in = cur;
+    a.out = other;
+    a.n = n;
+    a.c = hp.c;
+    a.L = lv.L;
+    a.tpm = lv.tpm;
+    a.cpm = lv.cpm;
+    a.chunk_base = lv.chunk_base;
+    a.merge_base = lv.merge_base;
+    a.zloc = pa.zloc;
+    a.zc = pa.zc;
+    a.P = pa.P;
+    a.side = pa.side;
+    a.key0 = pa.key0;
+    a.key1 = pa.key1;
+    {
+      ProfScope ps(2, st);
+      launch_merge_pass(a, eb, (uint64_t)lv.nmerge * lv.tpm, st);
+    }
+    {
+      ProfScope ps(3, st);
+      launch_patch(pa, (int)l, cur, other, eb, st);
+    }
+    cur = other;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MS_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
+  return MS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ms_shuffle_ex(void* dev_ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed, void* stream,
+                  const ms_config* cfg, unsigned long long* d_bits) {
+  g_err.clear();
+  return run_one(dev_ptr, n, elem_bytes, seed, reinterpret_cast<hipStream_t>(stream), cfg, d_bits, false);
+}
+
+int ms_shuffle(void* dev_ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed, void* stream) {
+  return ms_shuffle_ex(dev_ptr, n, elem_bytes, seed, stream, nullptr, nullptr);
+}
+
+int ms_permutation_ex(uint32_t* out, uint64_t n, uint64_t seed, void* stream, const ms_config* cfg,
+                      unsigned long long* d_bits) {
+  g_err.clear();
+  return run_one(out, n, 4, seed, reinterpret_cast<hipStream_t>(stream), cfg, d_bits, true);
+}
+
+int ms_permutation(uint32_t* out, uint64_t n, uint64_t seed) {
+  return ms_permutation_ex(out, n, seed, nullptr, nullptr, nullptr);
+}
+
+int ms_shuffle_batched_ex(void* const* ptrs, const uint64_t* sizes, const uint32_t* elem_bytes, uint32_t count,
+                          uint64_t seed, void* stream, const ms_config* cfg, unsigned long long* d_bits_per_array) {
+  g_err.clear();
+  if (count == 0) return MS_OK;
+  if (!ptrs || !sizes) return fail(MS_ERR_INVALID, "null pointer or size array");
+  for (uint32_t a = 0; a < count; ++a) {
+    const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
+    HostPlan hp;
+    int rc = make_plan(sizes[a], eb, cfg, hp);
+    if (rc) return rc;
+    if (sizes[a] > 0 && !ptrs[a]) return fail(MS_ERR_INVALID, "array %u: null pointer", a);
+  }
+  for (uint32_t a = 0; a < count; ++a) {
+    const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
+    int rc = run_one(ptrs[a], sizes[a], eb, seed + a, reinterpret_cast<hipStream_t>(stream), cfg,
+                     d_bits_per_array ? d_bits_per_array + a : nullptr, false);
+    if (rc) return rc;
+  }
+  return MS_OK;
+}
+
+int ms_shuffle_batched(void* const* ptrs, const uint64_t* sizes, uint32_t count, uint64_t seed, void* stream) {
+  return ms_shuffle_batched_ex(ptrs, sizes, nullptr, count, seed, stream, nullptr, nullptr);
+}
+
+int ms_plan(uint64_t n, uint32_t elem_bytes, const ms_config* cfg, ms_plan_info* out) {
+  g_err.clear();
+  if (!out) return fail(MS_ERR_INVALID, "null output");
+  HostPlan hp;
+  int rc = make_plan(n, elem_bytes, cfg, hp);
+  if (rc) return rc;
+  out->levels = hp.c;
+  out->lds_levels = hp.lam;
+  out->hbm_levels = hp.nlev;
+  out->leaf_B = hp.B;
+  out->leaves = hp.q;
+  out->scratch_bytes = scratch_of(hp);
+  out->pass_tiles = hp.pass_tiles;
+  return MS_OK;
+}
+
+uint64_t ms_scratch_bytes(uint64_t n, uint32_t elem_bytes) {
+  HostPlan hp;
+  if (make_plan(n, elem_bytes, nullptr, hp)) return 0;
+  return scratch_of(hp);
+}
+
+uint32_t ms_leaf_B_for(uint64_t n, uint32_t elem_bytes) {
+  (void)n;
+  (void)elem_bytes;
+  return kDefaultB;
+}
+
+int ms_device_status(void* stream, uint32_t* flags) {
+  g_err.clear();
+  DeviceCtx* dc;
+  int rc;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if ((rc = device_ctx(&dc))) return rc;
+  }
+  HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  uint32_t v = 0;
+  HIP_TRY(hipMemcpy(&v, dc->status, 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(dc->status, 0, 4));
+  if (flags) *flags = v;
+  return v ? MS_ERR_CAPACITY : MS_OK;
+}
+
+int ms_release(void) {
+  g_err.clear();
+  std::lock_guard<std::mutex> lk(g_mu);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceSynchronize());
+  DeviceCtx& d = g_dev[dev];
+  for (auto& kv : d.arenas) {
+    if (kv.second.data) HIP_TRY(hipFree(kv.second.data));
+    if (kv.second.plan) HIP_TRY(hipFree(kv.second.plan));
+  }
+  d.arenas.clear();
+  return MS_OK;
+}
+
+const char* ms_last_error(void) { return g_err.c_str(); }
+
+int ms_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_prof = on != 0;
+  return MS_OK;
+}
+
+int ms_profile_read(double ms_per_class[4], uint64_t launches_per_class[4]) {
+  g_err.clear();
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int i = 0; i < 4; ++i) {
+    if (ms_per_class) ms_per_class[i] = 0.0;
+    if (launches_per_class) launches_per_class[i] = 0;
+  }
+  int rc = MS_OK;
+  for (auto& r : g_prof_recs) {
+    float t = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+      rc = fail(MS_ERR_HIP, "profile event read failed");
+    } else if (r.cls >= 0 && r.cls < 4) {
+      if (ms_per_class) ms_per_class[r.cls] += t;
+      if (launches_per_class) launches_per_class[r.cls] += 1;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof_recs.clear();
+  return rc;
+}
+
+}  // extern "C"

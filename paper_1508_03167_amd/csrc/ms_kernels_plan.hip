@@ -1,0 +1,399 @@
+// ms_kernels_plan.hip -- the data-independent plan of the HBM merge levels.
+//
+// For every merge (L, m) handled by an HBM pass this computes, before any
+// element moves:
+//   * zeros among the coin flips per 128-flip granule (prefix within its
+//     32768-flip chunk) and per chunk (prefix within the merge), so the rank
+//     of any slot t -- how many A elements the coin-flip loop placed before
+//     t -- is a table lookup plus one Philox block;
+//   * the break step P: the loop of Algorithm 2 stops on the first flip whose
+//     side is already empty, i.e. at the (n1+1)-th zero or the (n2+1)-th one,
+//     whichever comes first; it has consumed P+1 flips (Lemma 1's proof);
+//   * the insertion loop (second loop of Algorithm 2): for i = P..N-1 it swaps
+//     slot i with a slot drawn uniformly in [0, i].  Its net effect is a small
+//     set of slots whose final value comes from another slot of the pre-
+//     insertion array C0.  Slots P..N-1 (one per step) are kept densely per
+//     merge; every step whose target j differs from i adds a "target entry"
+//     (j, i), bucketed by j.  Every slot is then resolved on its own:
+//       - slot x < P or x targeted by a later step: the last step i that
+//         targets x left C0[i] there;
+//       - slot p >= P otherwise holds what slot j_p held just before step p:
+//         the last earlier step targeting j_p left C0 of that step, or, if
+//         j_p >= P is itself a step before p, what j_p's own step fetched
+//         (followed recursively), or else C0[j_p];
+//     and is finally mapped to the input offset C0 reads it from.
+#include "ms_device.hpp"
+#include "ms_plan.hpp"
+
+namespace ms {
+
+__device__ __forceinline__ int level_of_chunk(const PlanArgs& pa, uint64_t idx) {
+  int l = (int)pa.nlev - 1;
+  while (l > 0 && pa.lev[l].chunk_base > idx) --l;
+  return l;
+}
+__device__ __forceinline__ int level_of_merge(const PlanArgs& pa, uint64_t idx) {
+  int l = (int)pa.nlev - 1;
+  while (l > 0 && pa.lev[l].merge_base > idx) --l;
+  return l;
+}
+__device__ __forceinline__ int level_of_wg(const PlanArgs& pa, uint64_t idx) {
+  int l = (int)pa.nlev - 1;
+  while (l > 0 && pa.lev[l].wg_base > idx) --l;
+  return l;
+}
+
+struct MergeGeom {
+  uint64_t s;   // first element
+  uint32_t n1, n2, N;
+};
+
+__device__ __forceinline__ MergeGeom merge_geom(const PlanArgs& pa, uint32_t L, uint32_t m) {
+  const uint64_t i0 = (uint64_t)m << L;
+  const uint64_t s = bound(pa.n, i0, pa.c);
+  const uint64_t mid = bound(pa.n, i0 + (1ull << (L - 1)), pa.c);
+  const uint64_t e = bound(pa.n, i0 + (1ull << L), pa.c);
+  MergeGeom g;
+  g.s = s;
+  g.n1 = (uint32_t)(mid - s);
+  g.n2 = (uint32_t)(e - mid);
+  g.N = (uint32_t)(e - s);
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// 1. zeros per granule and per chunk
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) plan_count_kernel(PlanArgs pa) {
+  __shared__ uint32_t tmp[8];
+  const uint64_t chunk = blockIdx.x;
+  const int l = level_of_chunk(pa, chunk);
+  const HbmLevel& lv = pa.lev[l];
+  const uint64_t rel = chunk - lv.chunk_base;
+  const uint32_t m = (uint32_t)(rel / lv.cpm);
+  const uint32_t ch = (uint32_t)(rel % lv.cpm);
+  const Key key{pa.key0, pa.key1};
+  const uint32_t g = (ch << kChunkGranLog) + threadIdx.x;
+  const W4 f = flip_block(g, m, lv.L, key);
+  const uint32_t z = 128u - (uint32_t)(__popc(f.w[0]) + __popc(f.w[1]) + __popc(f.w[2]) + __popc(f.w[3]));
+  uint32_t total;
+  const uint32_t ex = block_excl_scan<256>(z, tmp, &total);
+  pa.zloc[(chunk << kChunkGranLog) + threadIdx.x] = (uint16_t)ex;
+  if (threadIdx.x == 0) pa.ctot[chunk] = total;
+}
+
+// Position (0..127) of the r-th zero (want_one = 0) or one (want_one = 1) of a block.
+__device__ int select_in_block(const W4& f, uint32_t r, int want_one) {
+  for (int w = 0; w < 4; ++w) {
+    const uint32_t word = want_one ? f.w[w] : ~f.w[w];
+    const uint32_t c = (uint32_t)__popc(word);
+    if (r < c) return 32 * w + select_one(word, (int)r);
+    r -= c;
+  }
+  return 128;  // not reached for a valid r
+}
+
+// Slot of the (target+1)-th zero (want_one = 0) or one in chunk ch of merge m.
+__device__ uint32_t locate_in_chunk(const PlanArgs& pa, uint64_t chunk_global, uint32_t ch, uint32_t m,
+                                    uint32_t L, uint32_t r, int want_one) {
+  const uint16_t* zl = pa.zloc + (chunk_global << kChunkGranLog);
+  // largest granule g with (zeros or ones before g) <= r
+  int lo = 0, hi = 255;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const uint32_t before = want_one ? ((uint32_t)mid << kGranLog) - zl[mid] : zl[mid];
+    if (before <= r) lo = mid; else hi = mid - 1;
+  }
+  const uint32_t before = want_one ? ((uint32_t)lo << kGranLog) - zl[lo] : zl[lo];
+  const uint32_t gi = (ch << kChunkGranLog) + (uint32_t)lo;
+  const W4 f = flip_block(gi, m, L, Key{pa.key0, pa.key1});
+  const int pos = select_in_block(f, r - before, want_one);
+  return (gi << kGranLog) + (uint32_t)pos;
+}
+
+// ---------------------------------------------------------------------------
+// 2. per merge: chunk prefix, break step P and the side that ran out
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) plan_merge_kernel(PlanArgs pa) {
+  __shared__ uint32_t tmp[8];
+  __shared__ uint32_t bestA, bestB, resA, resB;
+  const uint64_t gm = blockIdx.x;
+  const int l = level_of_merge(pa, gm);
+  const HbmLevel& lv = pa.lev[l];
+  const uint32_t m = (uint32_t)(gm - lv.merge_base);
+  const uint32_t L = lv.L;
+  const MergeGeom g = merge_geom(pa, L, m);
+  const uint64_t cbase = lv.chunk_base + (uint64_t)m * lv.cpm;
+  if (threadIdx.x == 0) {
+    bestA = kNone32;
+    bestB = kNone32;
+  }
+  uint32_t running = 0;
+  for (uint32_t b = 0; b < lv.cpm; b += 256) {
+    const uint32_t idx = b + threadIdx.x;
+    const uint32_t v = idx < lv.cpm ? pa.ctot[cbase + idx] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<256>(v, tmp, &tot);
+    if (idx < lv.cpm) {
+      const uint32_t z0 = running + ex;
+      pa.zc[cbase + idx] = z0;
+      // the (n1+1)-th zero / (n2+1)-th one fall in this chunk?
+      if (z0 <= g.n1 && (uint64_t)g.n1 < (uint64_t)z0 + v) atomicMin(&bestA, idx);
+      const uint64_t o0 = ((uint64_t)idx << kChunkLog) - z0;
+      const uint64_t ov = (1ull << kChunkLog) - v;
+      if (o0 <= g.n2 && g.n2 < o0 + ov) atomicMin(&bestB, idx);
+    }
+    running += tot;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    resA = kNone32;
+    if (bestA != kNone32)
+      resA = locate_in_chunk(pa, cbase + bestA, bestA, m, L, g.n1 - pa.zc[cbase + bestA], 0);
+  }
+  if (threadIdx.x == 64) {
+    resB = kNone32;
+    if (bestB != kNone32) {
+      const uint32_t o0 = (bestB << kChunkLog) - pa.zc[cbase + bestB];
+      resB = locate_in_chunk(pa, cbase + bestB, bestB, m, L, g.n2 - o0, 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t P = resA < resB ? resA : resB;
+    pa.P[gm] = P;
+    pa.side[gm] = resA < resB ? 0 : 1;
+    pa.kcnt[gm] = g.N - P;
+    atomicAdd(pa.bits, (unsigned long long)P + 1ull);
+  }
+  const uint64_t bb = lv.bucket_base + (uint64_t)m * lv.bpm;
+  for (uint32_t b = threadIdx.x; b < lv.bpm; b += 256) {
+    pa.bcnt[bb + b] = 0;
+    pa.bfill[bb + b] = 0;
+  }
+}
+
+__device__ __forceinline__ uint32_t tail_draw(const PlanArgs& pa, uint32_t L, uint32_t m, uint32_t i,
+                                              uint32_t* bits) {
+  const Key key{pa.key0, pa.key1};
+  const W4 db = draw_block(i >> 2, m, L, key);
+  return fdr_draw((uint64_t)i + 1, db.w[i & 3], L, m, i, key, bits);
+}
+
+struct TailWg {
+  const HbmLevel* lv;
+  uint32_t m, w;
+  MergeGeom g;
+  uint32_t P, k;
+  uint64_t gm, bb;
+};
+
+__device__ __forceinline__ TailWg tail_wg(const PlanArgs& pa, uint64_t wg) {
+  TailWg t;
+  const int l = level_of_wg(pa, wg);
+  t.lv = &pa.lev[l];
+  const uint64_t rel = wg - t.lv->wg_base;
+  t.m = (uint32_t)(rel / t.lv->wpm);
+  t.w = (uint32_t)(rel % t.lv->wpm);
+  t.g = merge_geom(pa, t.lv->L, t.m);
+  t.gm = t.lv->merge_base + t.m;
+  t.P = pa.P[t.gm];
+  t.k = t.g.N - t.P;
+  t.bb = t.lv->bucket_base + (uint64_t)t.m * t.lv->bpm;
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// 3. insertion-loop draws: count target entries per bucket (and the bits)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) tail_count_kernel(PlanArgs pa) {
+  __shared__ uint64_t red[4];
+  const TailWg t = tail_wg(pa, blockIdx.x);
+  uint32_t bits = 0;
+  for (uint32_t d = t.w * 256 + threadIdx.x; d < t.k; d += t.lv->wpm * 256) {
+    const uint32_t i = t.P + d;
+    const uint32_t j = tail_draw(pa, t.lv->L, t.m, i, &bits);
+    if (j != i) atomicAdd(&pa.bcnt[t.bb + (j >> kBucketLog)], 1u);
+  }
+  const uint64_t s = block_sum_u64<256>(bits, red);
+  if (threadIdx.x == 0 && s) atomicAdd(pa.bits, (unsigned long long)s);
+}
+
+// ---------------------------------------------------------------------------
+// 4. exclusive scans (3 phases): counts -> offsets, total at out[count]
+// ---------------------------------------------------------------------------
+constexpr int kScanPer = 2048;  // items per workgroup
+
+__global__ void __launch_bounds__(256) scan_reduce_kernel(const uint32_t* __restrict__ in, uint64_t count,
+                                                          uint32_t* __restrict__ part) {
+  __shared__ uint32_t tmp[8];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanPer;
+  uint32_t s = 0;
+  for (int k = 0; k < kScanPer / 256; ++k) {
+    const uint64_t i = base + (uint64_t)k * 256 + threadIdx.x;
+    if (i < count) s += in[i];
+  }
+  uint32_t tot;
+  block_excl_scan<256>(s, tmp, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) scan_top_kernel(uint32_t* part, uint32_t nparts, uint32_t* out_end,
+                                                        uint64_t cap, uint32_t* status, uint32_t flag) {
+  __shared__ uint32_t tmp[20];
+  uint32_t running = 0;
+  for (uint32_t b = 0; b < nparts; b += 1024) {
+    const uint32_t idx = b + threadIdx.x;
+    const uint32_t v = idx < nparts ? part[idx] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<1024>(v, tmp, &tot);
+    if (idx < nparts) part[idx] = running + ex;
+    running += tot;
+  }
+  if (threadIdx.x == 0) {
+    *out_end = running;
+    if ((uint64_t)running > cap) atomicOr(status, flag);
+  }
+}
+
+__global__ void __launch_bounds__(256) scan_down_kernel(const uint32_t* __restrict__ in, uint64_t count,
+                                                        const uint32_t* __restrict__ part,
+                                                        uint32_t* __restrict__ out) {
+  __shared__ uint32_t tmp[8];
+  constexpr int kPer = kScanPer / 256;
+  const uint64_t base = (uint64_t)blockIdx.x * kScanPer + (uint64_t)threadIdx.x * kPer;
+  uint32_t v[kPer];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    v[k] = base + k < count ? in[base + k] : 0u;
+    s += v[k];
+  }
+  const uint32_t ex = block_excl_scan<256>(s, tmp, nullptr);
+  uint32_t run = part[blockIdx.x] + ex;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (base + k < count) out[base + k] = run;
+    run += v[k];
+  }
+}
+
+static void launch_scan(const uint32_t* in, uint64_t count, uint32_t* part, uint32_t* out, uint64_t cap,
+                        uint32_t* status, uint32_t flag, hipStream_t st) {
+  const uint32_t nparts = (uint32_t)((count + kScanPer - 1) / kScanPer);
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nparts), dim3(256), 0, st, in, count, part);
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, st, part, nparts, out + count, cap, status, flag);
+  hipLaunchKernelGGL(scan_down_kernel, dim3(nparts), dim3(256), 0, st, in, count, part, out);
+}
+
+// ---------------------------------------------------------------------------
+// 5. insertion-loop draws again: scatter the target entries into buckets
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) tail_scatter_kernel(PlanArgs pa) {
+  const TailWg t = tail_wg(pa, blockIdx.x);
+  uint32_t bits = 0;
+  for (uint32_t d = t.w * 256 + threadIdx.x; d < t.k; d += t.lv->wpm * 256) {
+    const uint32_t i = t.P + d;
+    const uint32_t j = tail_draw(pa, t.lv->L, t.m, i, &bits);
+    if (j == i) continue;
+    const uint64_t b = t.bb + (j >> kBucketLog);
+    const uint64_t slot = (uint64_t)pa.boff[b] + atomicAdd(&pa.bfill[b], 1u);
+    if (slot < pa.pool_cap) {
+      pa.pool_x[slot] = j;
+      pa.pool_step[slot] = i;
+    }
+  }
+}
+
+// Largest step s' < below among the steps that target slot y (y's own step excluded).
+__device__ __forceinline__ uint32_t max_target(const PlanArgs& pa, uint64_t bb, uint32_t y, uint32_t below) {
+  const uint64_t b = bb + (y >> kBucketLog);
+  const uint64_t lo = pa.boff[b];
+  uint64_t hi = lo + pa.bcnt[b];
+  if (hi > pa.pool_cap) hi = pa.pool_cap;
+  uint32_t best = kNone32;
+  for (uint64_t e = lo; e < hi; ++e) {
+    const uint32_t x = pa.pool_x[e];
+    const uint32_t st = pa.pool_step[e];
+    if (x == y && st < below && (best == kNone32 || st > best)) best = st;
+  }
+  return best;
+}
+
+// Merge-relative input offset of C0[src] (the array before the insertion loop).
+__device__ __forceinline__ uint32_t c0_offset(const PlanArgs& pa, const HbmLevel& lv, uint32_t m,
+                                              const MergeGeom& g, uint32_t P, uint32_t side, uint32_t src) {
+  if (src >= P) return side == 0 ? src : src - g.n2;
+  const uint64_t cglob = lv.chunk_base + (uint64_t)m * lv.cpm + (src >> kChunkLog);
+  const uint32_t gi = src >> kGranLog;
+  const W4 f = flip_block(gi, m, lv.L, Key{pa.key0, pa.key1});
+  const uint32_t wsel = (src >> 5) & 3;
+  uint32_t z = pa.zc[cglob] + pa.zloc[(cglob << kChunkGranLog) + (gi & 255)];
+  for (uint32_t w = 0; w < wsel; ++w) z += 32u - (uint32_t)__popc(f.w[w]);
+  const uint32_t word = f.w[wsel];
+  const uint32_t bit = src & 31;
+  z += (uint32_t)__popc(~word & ((1u << bit) - 1u));
+  return ((word >> bit) & 1u) ? g.n1 + (src - z) : z;
+}
+
+// ---------------------------------------------------------------------------
+// 6. resolve every touched slot: where its final value comes from
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) tail_resolve_kernel(PlanArgs pa) {
+  const TailWg t = tail_wg(pa, blockIdx.x);
+  const HbmLevel& lv = *t.lv;
+  const uint32_t side = pa.side[t.gm];
+  const uint64_t toff = pa.toff[t.gm];
+  // slots P..N-1, one per step
+  for (uint32_t d = t.w * 256 + threadIdx.x; d < t.k; d += lv.wpm * 256) {
+    const uint32_t x = t.P + d;
+    uint32_t out = kNone32;
+    if (max_target(pa, t.bb, x, kNone32) == kNone32) {
+      // no later step targets x: it keeps what its own step fetched from j_x
+      uint32_t dummy = 0;
+      uint32_t s = x;
+      uint32_t y = tail_draw(pa, lv.L, t.m, x, &dummy);
+      uint32_t src;
+      for (;;) {
+        const uint32_t q = max_target(pa, t.bb, y, s);
+        if (q != kNone32) { src = q; break; }      // last earlier step writing y
+        if (y >= t.P && y < s) {                   // y's own step wrote it
+          s = y;
+          y = tail_draw(pa, lv.L, t.m, y, &dummy);
+          continue;
+        }
+        src = y;                                   // untouched since C0
+        break;
+      }
+      out = c0_offset(pa, lv, t.m, t.g, t.P, side, src);
+    }
+    if (toff + d < pa.tail_cap) pa.tail_src[toff + d] = out;
+  }
+  // target entries: final if theirs is the last step targeting the slot
+  const uint64_t lo = pa.boff[t.bb];
+  uint64_t hi = pa.boff[t.bb + lv.bpm];
+  if (hi > pa.pool_cap) hi = pa.pool_cap;
+  for (uint64_t e = lo + (uint64_t)t.w * 256 + threadIdx.x; e < hi; e += (uint64_t)lv.wpm * 256) {
+    const uint32_t x = pa.pool_x[e];
+    const uint32_t st = pa.pool_step[e];
+    uint32_t out = kNone32;
+    if (max_target(pa, t.bb, x, kNone32) == st) out = c0_offset(pa, lv, t.m, t.g, t.P, side, st);
+    pa.pool_src[e] = out;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launcher
+// ---------------------------------------------------------------------------
+void launch_plan(const PlanArgs& pa, hipStream_t st) {
+  if (pa.nlev == 0) return;
+  hipLaunchKernelGGL(plan_count_kernel, dim3((uint32_t)pa.total_chunks), dim3(256), 0, st, pa);
+  hipLaunchKernelGGL(plan_merge_kernel, dim3((uint32_t)pa.total_merges), dim3(256), 0, st, pa);
+  launch_scan(pa.kcnt, pa.total_merges, pa.part, pa.toff, pa.tail_cap, pa.status, 2u, st);
+  hipLaunchKernelGGL(tail_count_kernel, dim3((uint32_t)pa.total_tail_wgs), dim3(256), 0, st, pa);
+  launch_scan(pa.bcnt, pa.total_buckets, pa.part, pa.boff, pa.pool_cap, pa.status, 1u, st);
+  hipLaunchKernelGGL(tail_scatter_kernel, dim3((uint32_t)pa.total_tail_wgs), dim3(256), 0, st, pa);
+  hipLaunchKernelGGL(tail_resolve_kernel, dim3((uint32_t)pa.total_tail_wgs), dim3(256), 0, st, pa);
+}
+
+}  // namespace ms

@@ -1,0 +1,77 @@
+// ms_plan.hpp -- launch plan shared by the host runtime and the kernels.
+//
+// MergeShuffle (Algorithm MergeShuffle; shuffle() listing, Appendix A.2)
+// splits n elements into q = 2^c blocks [n*i/q, n*(i+1)/q), c the least level
+// count with (n >> c) <= cutoff, shuffles each block with Fisher-Yates and
+// then merges adjacent blocks for levels L = 1..c.  On the GPU:
+//   * the leaf kernel shuffles each leaf in LDS and runs the first `lds_levels`
+//     merge levels inside the same workgroup (a super-block of 2^lds_levels
+//     leaves fits in LDS);
+//   * every remaining level is one streaming pass over HBM, prepared by a
+//     data-independent plan: coin-flip counts per 128-flip granule (one
+//     Philox block) and per 32768-flip chunk, the break step P of every merge,
+//     and the insertion-loop ("tail") resolution into a list of patches.
+#pragma once
+
+#include <stdint.h>
+
+namespace ms {
+
+constexpr int kMaxLevels = 32;
+constexpr uint32_t kGranLog = 7;       // 128 flips per granule (one Philox block)
+constexpr uint32_t kChunkGranLog = 8;  // 256 granules per chunk
+constexpr uint32_t kChunkLog = kGranLog + kChunkGranLog;  // 32768 flips per chunk
+constexpr uint32_t kBucketLog = 12;    // tail-entry buckets of 4096 positions
+
+// One merge level that runs as an HBM pass.
+struct HbmLevel {
+  uint32_t L;             // level, 1..c
+  uint32_t nmerge;        // q >> L
+  uint32_t nmax;          // largest merge size at this level
+  uint32_t cpm;           // flip chunks per merge
+  uint32_t bpm;           // tail buckets per merge
+  uint32_t wpm;           // tail workgroups per merge
+  uint32_t tpm;           // merge-pass tiles per merge
+  uint32_t pad;
+  uint64_t chunk_base;    // first chunk of this level (ctot, zc); granules at chunk_base << 8
+  uint64_t merge_base;    // first merge of this level in the per-merge arrays
+  uint64_t bucket_base;   // first bucket of this level
+  uint64_t pool_cap;      // bound on the tail entries of this level (grid sizing)
+  uint64_t wg_base;       // first workgroup of this level in the tail kernels
+};
+
+struct PlanArgs {
+  uint64_t n;
+  uint32_t c;             // levels
+  uint32_t lds_levels;    // levels run inside the leaf kernel
+  uint32_t nlev;          // HBM levels: L = lds_levels+1 .. c
+  uint32_t pad0;
+  uint32_t key0, key1;    // seed
+  uint64_t total_chunks;
+  uint64_t total_merges;
+  uint64_t total_buckets;
+  uint64_t total_tail_wgs;
+  uint64_t pool_cap;      // capacity of the target-entry pool (all levels)
+  uint64_t tail_cap;      // capacity of the dense per-step tail arrays (all levels)
+  // device arrays
+  uint16_t* zloc;         // per granule: zeros before it within its chunk
+  uint32_t* ctot;         // per chunk: zeros in the chunk
+  uint32_t* zc;           // per chunk: zeros before it within its merge
+  uint32_t* P;            // per merge: break step (coin-flip prefix length)
+  uint8_t* side;          // per merge: 0 = A ran out first, 1 = B ran out first
+  uint32_t* kcnt;         // per merge: insertion steps N - P
+  uint32_t* toff;         // per merge (+1): exclusive prefix of kcnt
+  uint32_t* tail_src;     // per insertion step i: input offset of slot i's final value, or ~0
+  uint32_t* bcnt;         // per bucket: target entries (step i, slot j_i < i)
+  uint32_t* bfill;        // per bucket: fill cursor
+  uint32_t* boff;         // per bucket (+1): exclusive prefix of bcnt
+  uint32_t* part;         // scan partials
+  uint32_t* pool_x;       // target entry: merge-relative slot j
+  uint32_t* pool_step;    // target entry: the step i that writes C0[i] into slot j
+  uint32_t* pool_src;     // target entry: input offset of slot j's final value, or ~0
+  unsigned long long* bits;
+  uint32_t* status;
+  HbmLevel lev[kMaxLevels];
+};
+
+}  // namespace ms

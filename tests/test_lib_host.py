@@ -1,0 +1,63 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every symbol the header declares, plans calls, and rejects bad arguments
+before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_1508_03167_amd as M
+
+    return M, M.lib()
+
+
+def test_exports_every_declared_symbol():
+    M, L = _lib()
+    hdr = open(os.path.join(ROOT, "include", "mergeshuffle.h")).read()
+    names = set(re.findall(r"^\s*(?:int|uint64_t|uint32_t|const char\*)\s+(ms_\w+)\s*\(", hdr, re.M))
+    assert len(names) >= 14
+    for nm in names:
+        assert hasattr(L, nm), nm
+    from paper_1508_03167_amd._lib import SYMBOLS
+
+    assert set(SYMBOLS) == names
+
+
+def test_plan_matches_the_driver_partition():
+    M, _ = _lib()
+    p = M.plan(1 << 20)
+    assert (p["levels"], p["leaves"], p["leaf_B"]) == (8, 256, 4096)
+    assert p["lds_levels"] + p["hbm_levels"] == 8
+    p = M.plan(1 << 30)
+    assert p["levels"] == 18 and p["lds_levels"] == 3 and p["hbm_levels"] == 15
+    assert p["scratch_bytes"] >= 4 << 30
+    p = M.plan(1 << 27, 16)
+    assert p["levels"] == 15
+    p = M.plan(4096)
+    assert p["levels"] == 0 and p["hbm_levels"] == 0 and p["scratch_bytes"] == 0
+    p = M.plan(8193)
+    assert p["levels"] == 1
+    p = M.plan(100000, 4, leaf_B=16, hbm_only=True)
+    assert p["lds_levels"] == 0 and p["levels"] == p["hbm_levels"]
+
+
+def test_rejects_bad_arguments_without_a_device():
+    M, L = _lib()
+    assert L.ms_shuffle(None, 10, 4, 1, None) == -1          # null pointer, n > 0
+    assert L.ms_shuffle(ctypes.c_void_p(16), 10, 12, 1, None) == -2   # element size
+    assert L.ms_shuffle(ctypes.c_void_p(16), 1 << 33, 4, 1, None) == -2  # n too large
+    assert L.ms_shuffle(ctypes.c_void_p(18), 10, 4, 1, None) == -1    # misaligned
+    cfg = M._lib.MSConfig(5000, 0, 0, 0)
+    assert L.ms_shuffle_ex(ctypes.c_void_p(16), 10, 4, 1, None, ctypes.byref(cfg), None) == -2
+    assert b"cutoff" in L.ms_last_error()
+    assert L.ms_shuffle_batched(None, None, 3, 1, None) == -1
+    assert L.ms_shuffle_batched(None, None, 0, 1, None) == 0
+    info = M._lib.MSPlanInfo()
+    assert L.ms_plan(10, 3, None, ctypes.byref(info)) == -2
+    assert L.ms_scratch_bytes(1 << 20, 4) > 4 << 20
+    assert L.ms_leaf_B_for(1 << 20, 4) == 4096
