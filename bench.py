@@ -2,11 +2,20 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--n-log2 30] [--no-cpu-baseline]
 
-A step is one complete shuffle (plan, leaf kernel, every merge pass and its
-patch) of the resident 4 GiB array.  Prints one JSON line with the whole-job
-throughput in Gelem/s, the roofline of the dominant kernel (the HBM merge
-pass: 2 * n * 4 algorithmic bytes per launch over its average HIP-event
-duration, against 8 TB/s) and the CPU oracle timed on a bounded sample.
+A step is one complete shuffle of the resident 4 GiB array: the plan, the
+leaf kernel (Fisher-Yates of every leaf plus the merge levels that fit in
+LDS) and every HBM merge pass with its insertion-loop patch.  The JSON line
+carries the whole-job throughput (Gelem/s), the roofline of the kernel class
+that takes most of the step (measured with HIP events around each launch on
+the library's stream), and the CPU oracle timed on a bounded sample.
+
+Roofline figures:
+  * merge pass (HBM-bound): algorithmic bytes per launch = 2 * n * 4 (every
+    element read once and written once), against 8 TB/s;
+  * leaf kernel (ALU-bound): algorithmic integer ops per element = the
+    Philox-4x32-10 work of the bits it draws (one 100-op block per 4 leaf
+    draws and per 128 coin flips of each LDS level) plus about 10 ops per
+    Fast Dice Roller draw, against 256 CUs x 64 lanes x 2.4 GHz.
 """
 import argparse
 import hashlib
@@ -19,6 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+ALU_PEAK_GOPS = 256 * 64 * 2.4  # int32 vector lane-ops per ns -> Gop/s: 39321.6
+PHILOX_OPS = 100.0
+FDR_OPS = 10.0
 
 
 def kernel_source_hash() -> str:
@@ -28,10 +40,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(n_bytes_alg: float):
-    """HBM bytes per merge-pass launch from the committed counter summary, if it
-    was taken on the current kernel source; else None."""
-    p = os.path.join(ROOT, "profiles", "merge_pass_n2^30_u32_traffic.json")
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
@@ -47,12 +59,12 @@ def cpu_baseline(n_log2: int):
     n = 1 << n_log2
     O.build(force=False)
     t = time.perf_counter()
-    _, bits = O.permutation(n, 4096, 7, threads=threads)
+    O.permutation(n, 4096, 7, threads=threads)
     dt = time.perf_counter() - t
-    return {"value": n / dt / 1e9, "unit": "Gelem/s", "cores": threads, "kind": "oracle",
+    return {"value": round(n / dt / 1e9, 4), "unit": "Gelem/s", "cores": threads, "kind": "oracle",
             "sample": f"one MergeShuffle of a uint32 identity array, n=2^{n_log2}, seed 7, cutoff 4096 "
-                      f"(same procedure as the GPU step at 1/{1 << (30 - n_log2)} the size), "
-                      f"{dt:.2f} s, OpenMP over blocks and over merges of a level"}
+                      f"(the GPU step's procedure at 1/{1 << max(0, 30 - n_log2)} of its size), {dt:.2f} s, "
+                      f"OpenMP over the blocks and over the merges of a level"}
 
 
 def main():
@@ -63,10 +75,22 @@ def main():
     ap.add_argument("--n-log2", type=int, default=30)
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-log2", type=int, default=26)
+    ap.add_argument("--cpu-sample-log2", type=int, default=27)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain device copies of 2^28 uint32 (1 GiB) for counter calibration")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        a = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_dispatch": 1 << 30}), flush=True)
+        return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (no multi-GPU path)"}))
         sys.exit(2)
 
     import torch
@@ -74,10 +98,8 @@ def main():
     import paper_1508_03167_amd as M
 
     n = 1 << args.n_log2
-    dev = torch.device("cuda:0")
-    x = torch.arange(n, dtype=torch.int32, device=dev)
+    x = torch.arange(n, dtype=torch.int32, device="cuda:0")
     plan = M.plan(n, 4)
-    stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         M.shuffle_(x, args.seed)
     torch.cuda.synchronize()
@@ -91,18 +113,33 @@ def main():
     t1 = time.perf_counter()
     M.profile_enable(False)
     ms_cls, cnt_cls = M.profile_read()
-    assert M.device_status() == 0
+    assert M.device_status() == 0, "plan pool overflow flagged"
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n / (ms_per_step / 1e3) / 1e9
 
-    pass_launches = max(cnt_cls["merge_pass"], 1)
-    pass_ms = ms_cls["merge_pass"] / pass_launches
-    alg_bytes = 2.0 * n * 4
-    achieved = alg_bytes / (pass_ms / 1e3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(alg_bytes),
-            "kernel": "merge_pass_kernel<uint32_t,8192>", "avg_launch_ms": round(pass_ms, 4),
-            "launches": cnt_cls["merge_pass"]}
+    def pass_roof():
+        launches = max(cnt_cls["merge_pass"], 1)
+        avg = ms_cls["merge_pass"] / launches
+        ach = 2.0 * n * 4 / (avg / 1e3) / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": traffic_from_profiles("merge_pass_n2^30_u32"),
+                "kernel": "merge_pass_kernel<uint32_t,4096,1>", "avg_launch_ms": round(avg, 4),
+                "launches": cnt_cls["merge_pass"], "alg_bytes_per_launch": 2 * n * 4}
+
+    def leaf_roof():
+        launches = max(cnt_cls["leaf"], 1)
+        avg = ms_cls["leaf"] / launches
+        ops_per_elem = PHILOX_OPS * (0.25 + plan["lds_levels"] / 128.0) + FDR_OPS
+        ach = ops_per_elem * n / (avg / 1e3) / 1e9
+        return {"bound": "alu", "achieved": round(ach, 1), "peak": ALU_PEAK_GOPS, "unit": "Gop/s",
+                "frac": round(ach / ALU_PEAK_GOPS, 4), "traffic": traffic_from_profiles("leaf_n2^30_u32"),
+                "kernel": "leaf_kernel<uint32_t,32768,1024>", "avg_launch_ms": round(avg, 4),
+                "launches": cnt_cls["leaf"], "alg_ops_per_launch": ops_per_elem * n,
+                "alg_bytes_per_launch": 2 * n * 4}
+
+    roofs = {"merge_pass": pass_roof(), "leaf": leaf_roof()}
+    dominant = max(("merge_pass", "leaf"), key=lambda k: ms_cls[k])
     breakdown = {k: round(v / args.steps, 3) for k, v in ms_cls.items()}
 
     out = {
@@ -122,7 +159,8 @@ def main():
                                f"cutoff 4096, resident in HBM",
                    "n": n, "levels": plan["levels"], "lds_levels": plan["lds_levels"],
                    "hbm_passes": plan["hbm_levels"], "parallelism": "single GPU"},
-        "roofline": roof,
+        "roofline": dict(roofs[dominant], dominant_kernel_class=dominant),
+        "roofline_other": roofs["leaf" if dominant == "merge_pass" else "merge_pass"],
         "ms_per_step_by_kernel_class": breakdown,
     }
     if not args.no_cpu_baseline:

@@ -18,7 +18,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mergeshuffle.h"
+#include "mergeshuffle.h"
 #include "ms_plan.hpp"
 
 namespace ms {
@@ -43,6 +43,7 @@ struct PassArgs {
   const uint32_t* P;
   const uint8_t* side;
   uint32_t key0, key1;
+  uint32_t vec_ok;
 };
 void launch_plan(const PlanArgs& pa, hipStream_t st);
 void launch_leaf(const LeafArgs& a, uint32_t eb, bool ident, uint64_t grid, hipStream_t st);
@@ -344,6 +345,7 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
     a.side = pa.side;
     a.key0 = pa.key0;
     a.key1 = pa.key1;
+    a.vec_ok = ((uintptr_t)cur % 16 == 0) ? 1u : 0u;
     {
       ProfScope ps(2, st);
       launch_merge_pass(a, eb, (uint64_t)lv.nmerge * lv.tpm, st);

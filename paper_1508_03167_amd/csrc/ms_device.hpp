@@ -55,6 +55,13 @@ __device__ __forceinline__ W4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
   return o;
 }
 
+// Word i (0..3) of a block, without indexing a private array.
+__device__ __forceinline__ uint32_t pick(const W4& x, uint32_t i) {
+  const uint32_t lo = (i & 1u) ? x.w[1] : x.w[0];
+  const uint32_t hi = (i & 1u) ? x.w[3] : x.w[2];
+  return (i & 2u) ? hi : lo;
+}
+
 // The 128 coin flips t = 128*g .. 128*g+127 of merge m at level L.
 __device__ __forceinline__ W4 flip_block(uint32_t g, uint32_t m, uint32_t L, Key key) {
   return philox(g, m, L, kDomFlip, key);
@@ -70,28 +77,14 @@ __device__ __forceinline__ int bitlen64(uint64_t x) { return 64 - __clzll(x); }
 // Fast Dice Roller in its jump form: instead of one bit at a time it reads at
 // once the d bits after which the range v first reaches k (least d with
 // v * 2^d >= k), which is the same bits in the same order with the same
-// result as the bit-at-a-time loop.  Returns a value in [0, k); adds the bits
-// consumed to *bits.  k <= 2^32.
-__device__ __noinline__ uint32_t fdr_draw_slow(uint64_t k, uint32_t w0, uint32_t L, uint32_t u, uint32_t d,
-                                               Key key, uint32_t* bits);
+// result as the bit-at-a-time loop.  Returns the value in [0, k) and the
+// number of bits consumed.  k <= 2^32.
+struct Draw {
+  uint32_t v;
+  uint32_t bits;
+};
 
-__device__ __forceinline__ uint32_t fdr_draw(uint64_t k, uint32_t w0, uint32_t L, uint32_t u, uint32_t d,
-                                             Key key, uint32_t* bits) {
-  if (k <= 1) return 0;
-  // Fast path: the first jump reads bitlen(k-1) bits of the primary word.
-  const int need = bitlen64(k - 1);
-  if (need <= 32) {
-    const uint32_t c = need == 32 ? w0 : (w0 >> (32 - need));
-    if ((uint64_t)c < k) {
-      *bits += (uint32_t)need;
-      return c;
-    }
-  }
-  return fdr_draw_slow(k, w0, L, u, d, key, bits);
-}
-
-__device__ __noinline__ uint32_t fdr_draw_slow(uint64_t k, uint32_t w0, uint32_t L, uint32_t u, uint32_t d,
-                                               Key key, uint32_t* bits) {
+__device__ __noinline__ Draw fdr_draw_slow(uint64_t k, uint32_t w0, uint32_t L, uint32_t u, uint32_t d, Key key) {
   uint64_t v = 1, c = 0;
   uint32_t buf = w0;
   int left = 32;
@@ -126,13 +119,37 @@ __device__ __noinline__ uint32_t fdr_draw_slow(uint64_t k, uint32_t w0, uint32_t
     v <<= jump;
     c = (c << jump) | x;
     used += (uint32_t)jump;
-    if (c < k) {
-      *bits += used;
-      return (uint32_t)c;
-    }
+    if (c < k) return Draw{(uint32_t)c, used};
     v -= k;
     c -= k;
   }
+}
+
+__device__ __forceinline__ Draw fdr_draw(uint64_t k, uint32_t w0, uint32_t L, uint32_t u, uint32_t d, Key key) {
+  if (k <= 1) return Draw{0u, 0u};
+  if (k <= (1ull << 31)) {
+    // Ranges stay below 2^32: run the loop in 32-bit arithmetic as long as
+    // the primary word lasts; restart in the general routine otherwise.
+    const uint32_t k32 = (uint32_t)k;
+    const int bk = 32 - __clz(k32 - 1);
+    uint32_t v = 1, c = 0, used = 0;
+    int left = 32;
+#pragma unroll 1
+    for (;;) {
+      int jump = bk - (32 - __clz(v));
+      if ((v << jump) <= k32 - 1) jump += 1;
+      if (jump > left) break;
+      const uint32_t x = jump == 32 ? w0 : ((w0 >> (left - jump)) & ((1u << jump) - 1u));
+      left -= jump;
+      used += (uint32_t)jump;
+      v <<= jump;
+      c = (c << jump) | x;
+      if (c < k32) return Draw{c, used};
+      v -= k32;
+      c -= k32;
+    }
+  }
+  return fdr_draw_slow(k, w0, L, u, d, key);
 }
 
 // Position (0..31) of the r-th zero bit (r counted from 0) of w, LSB first.

@@ -30,7 +30,6 @@
 
 namespace ms {
 
-constexpr int kLeafThreads = 1024;
 constexpr int kLeafMaxMerges = 64;  // at most 2^6 leaves per super-block
 
 struct LeafArgs {
@@ -54,12 +53,6 @@ __device__ __forceinline__ uint4 ident_value<uint4>(uint64_t i) {
   return make_uint4((uint32_t)i, (uint32_t)(i >> 32), 0u, 0u);
 }
 
-template <int LMAX>
-struct FyAux {
-  uint32_t head[LMAX];   // list head per target slot; later up() per slot
-  uint16_t next[LMAX];   // next step in the same target list
-};
-
 template <int SCAP>
 struct MergeAux {
   static constexpr int kWords = SCAP / 32 + 8 * kLeafMaxMerges + 8;
@@ -67,115 +60,156 @@ struct MergeAux {
   uint32_t wpre[kWords];
 };
 
-template <int SCAP, int LMAX>
-union LeafAux {
-  FyAux<LMAX> fy;
-  MergeAux<SCAP> mg;
-};
+// Swap a 16-bit entry of a packed LDS array (two entries per 32-bit word);
+// returns the old entry.
+__device__ __forceinline__ uint32_t xchg_u16(uint16_t* arr, uint32_t pos, uint32_t val) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(arr) + (pos >> 1);
+  const uint32_t sh = (pos & 1u) * 16u;
+  uint32_t cur = *w;
+  for (;;) {
+    const uint32_t nv = (cur & ~(0xFFFFu << sh)) | (val << sh);
+    const uint32_t prev = atomicCAS(w, cur, nv);
+    if (prev == cur) return (cur >> sh) & 0xFFFFu;
+    cur = prev;
+  }
+}
 
-// Fisher-Yates of one leaf [lb, lb+b) of the LDS array, unit u.
-template <typename E, int LMAX>
-__device__ __forceinline__ void leaf_fisher_yates(E* data, FyAux<LMAX>& fy, uint32_t lb, uint32_t b, uint32_t u,
-                                                  Key key, uint32_t* bits) {
-  constexpr int NT = kLeafThreads;
-  constexpr int NB = (LMAX + 4 * NT - 1) / (4 * NT);
-  const int tid = threadIdx.x;
-  for (uint32_t x = tid; x < b; x += NT) fy.head[x] = kNone32;
-  __syncthreads();
-  uint32_t jr[NB][4];
+__device__ __forceinline__ uint32_t get16(uint32_t packed, int half) { return (packed >> (16 * half)) & 0xFFFFu; }
+
+// Fisher-Yates of every leaf of the super-block at once (Algorithm 1 per leaf).
+// Before the elements are loaded, the LDS data region holds, per super-block
+// slot, a 16-bit list head (steps targeting the slot, later up()) and a
+// 16-bit list link.  Each thread owns blocks of 4 consecutive steps of one
+// leaf (the steps whose draws share one Philox block) and returns, packed two
+// per register, the leaf-relative source F of each of its slots.
+template <int BPT>
+__device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, uint32_t lb, uint32_t b, uint32_t u,
+                                                uint32_t lt, uint32_t tpl, Key key, uint32_t* bits,
+                                                uint32_t (&F)[BPT][2]) {
+  constexpr uint32_t NONE = 0xFFFFu;
+  uint32_t J[BPT][2];
+  // 1. draws j_r for r = b-1..1 and the list of steps per target slot
 #pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const uint32_t g = tid + k * NT;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) jr[k][e] = kNone32;
+  for (int k = 0; k < BPT; ++k) {
+    const uint32_t g = lt + tpl * k;
+    J[k][0] = J[k][1] = 0xFFFFFFFFu;
     if (4 * g < b) {
       const W4 db = draw_block(g, u, 0, key);
+      uint32_t jj[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const uint32_t r = 4 * g + e;
+        jj[e] = NONE;
         if (r >= 1 && r < b) {
-          const uint32_t j = fdr_draw((uint64_t)r + 1, db.w[e], 0, u, r, key, bits);
-          jr[k][e] = j;
-          const uint32_t old = atomicExch(&fy.head[j], r);
-          fy.next[r] = (uint16_t)(old == kNone32 ? 0xFFFFu : old);
+          const Draw dr = fdr_draw((uint64_t)r + 1, db.w[e], 0, u, r, key);
+          *bits += dr.bits;
+          jj[e] = dr.v;
         }
       }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t r = 4 * g + e;
+        if (jj[e] != NONE) link[lb + r] = (uint16_t)xchg_u16(head, lb + jj[e], r);
+      }
+      J[k][0] = jj[0] | (jj[1] << 16);
+      J[k][1] = jj[2] | (jj[3] << 16);
     }
   }
   __syncthreads();
-  uint32_t upv[NB][4], nx[NB][4];
+  // 2. up(x) = least step > x targeting x; nxt(r) = least step > r targeting j_r
+  uint32_t U[BPT][2], X[BPT][2];
 #pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const uint32_t g = tid + k * NT;
+  for (int k = 0; k < BPT; ++k) {
+    const uint32_t g = lt + tpl * k;
+    U[k][0] = U[k][1] = X[k][0] = X[k][1] = 0xFFFFFFFFu;
+    if (4 * g < b) {
+      uint32_t pu[4], px[4], bu[4], bx[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint32_t x = 4 * g + e;
-      upv[k][e] = kNone32;
-      nx[k][e] = kNone32;
-      if (x < b) {
-        uint32_t best = kNone32;
-        for (uint32_t p = fy.head[x]; p != kNone32;) {
-          if (p > x && p < best) best = p;
-          const uint32_t q = fy.next[p];
-          p = q == 0xFFFFu ? kNone32 : q;
-        }
-        upv[k][e] = best;
-        if (x >= 1) {
-          uint32_t best2 = kNone32;
-          for (uint32_t p = fy.head[jr[k][e]]; p != kNone32;) {
-            if (p > x && p < best2) best2 = p;
-            const uint32_t q = fy.next[p];
-            p = q == 0xFFFFu ? kNone32 : q;
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t x = 4 * g + e;
+        const uint32_t jx = get16(J[k][e >> 1], e & 1);
+        pu[e] = x < b ? (uint32_t)head[lb + x] : NONE;
+        px[e] = (x >= 1 && x < b) ? (uint32_t)head[lb + jx] : NONE;
+        bu[e] = NONE;
+        bx[e] = NONE;
+      }
+      // walk the eight lists side by side
+      for (;;) {
+        bool any = false;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t x = 4 * g + e;
+          if (pu[e] != NONE) {
+            any = true;
+            if (pu[e] > x && pu[e] < bu[e]) bu[e] = pu[e];
+            pu[e] = link[lb + pu[e]];
           }
-          nx[k][e] = best2;
+          if (px[e] != NONE) {
+            any = true;
+            if (px[e] > x && px[e] < bx[e]) bx[e] = px[e];
+            px[e] = link[lb + px[e]];
+          }
         }
+        if (!any) break;
       }
+      U[k][0] = bu[0] | (bu[1] << 16);
+      U[k][1] = bu[2] | (bu[3] << 16);
+      X[k][0] = bx[0] | (bx[1] << 16);
+      X[k][1] = bx[2] | (bx[3] << 16);
     }
   }
   __syncthreads();
+  // 3. head[] now holds up(x)
 #pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const uint32_t g = tid + k * NT;
+  for (int k = 0; k < BPT; ++k) {
+    const uint32_t g = lt + tpl * k;
 #pragma unroll
     for (int e = 0; e < 4; ++e)
-      if (4 * g + e < b) fy.head[4 * g + e] = upv[k][e];
+      if (4 * g + e < b) head[lb + 4 * g + e] = (uint16_t)get16(U[k][e >> 1], e & 1);
   }
   __syncthreads();
-  E val[NB][4];
+  // 4. F[r] = top(nxt(r)) or j_r; F[0] = top(0); top() follows up() to its end
 #pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const uint32_t g = tid + k * NT;
+  for (int k = 0; k < BPT; ++k) {
+    const uint32_t g = lt + tpl * k;
+    F[k][0] = F[k][1] = 0u;
+    if (4 * g < b) {
+      uint32_t t[4];
+      bool walk[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint32_t x = 4 * g + e;
-      if (x < b) {
-        uint32_t src;
-        uint32_t t = x == 0 ? 0u : nx[k][e];
-        if (x != 0 && t == kNone32) {
-          src = jr[k][e];
-        } else {
-          while (fy.head[t] != kNone32) t = fy.head[t];
-          src = t;
-        }
-        val[k][e] = data[lb + src];
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t x = 4 * g + e;
+        const uint32_t nx = get16(X[k][e >> 1], e & 1);
+        walk[e] = x < b && (x == 0 || nx != NONE);
+        t[e] = x == 0 ? 0u : (nx != NONE ? nx : get16(J[k][e >> 1], e & 1));
       }
+      for (;;) {
+        bool any = false;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (walk[e]) {
+            const uint32_t up = head[lb + t[e]];
+            if (up != NONE) { t[e] = up; any = true; }
+            else walk[e] = false;
+          }
+        }
+        if (!any) break;
+      }
+      F[k][0] = (t[0] & 0xFFFFu) | (t[1] << 16);
+      F[k][1] = (t[2] & 0xFFFFu) | (t[3] << 16);
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const uint32_t g = tid + k * NT;
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (4 * g + e < b) data[lb + 4 * g + e] = val[k][e];
   }
   __syncthreads();
 }
 
-// Insertion loop of one merge [s0, s0+N) in LDS by one wave, groups of 64 steps.
+// Insertion loop of one merge [s0, s0+N) in LDS by one wave, groups of 64
+// steps.  `seen` is a zeroed bitmap over the super-block's slots.  A group
+// whose targets all lie below the group and are pairwise distinct touches
+// disjoint slots, so its swaps commute and run at once; other groups resolve
+// their steps against each other lane by lane.
 template <typename E>
-__device__ __forceinline__ void lds_merge_tail(E* data, uint32_t s0, uint32_t N, uint32_t P, uint32_t L,
-                                               uint32_t gm, Key key, uint32_t* bits) {
+__device__ __forceinline__ void lds_merge_tail(E* data, uint32_t* seen, uint32_t s0, uint32_t N, uint32_t P,
+                                               uint32_t L, uint32_t gm, Key key, uint32_t* bits) {
   const int lane = threadIdx.x & 63;
   for (uint32_t i0 = P; i0 < N; i0 += 64) {
     const uint32_t i = i0 + lane;
@@ -183,7 +217,29 @@ __device__ __forceinline__ void lds_merge_tail(E* data, uint32_t s0, uint32_t N,
     uint32_t j = kNone32;
     if (act) {
       const W4 db = draw_block(i >> 2, gm, L, key);
-      j = fdr_draw((uint64_t)i + 1, db.w[i & 3], L, gm, i, key, bits);
+      const Draw dr = fdr_draw((uint64_t)i + 1, pick(db, i & 3), L, gm, i, key);
+      j = dr.v;
+      *bits += dr.bits;
+    }
+    bool clash = act && j >= i0;
+    if (act && j < i0) {
+      const uint32_t bit = 1u << ((s0 + j) & 31);
+      const uint32_t old = atomicOr(&seen[(s0 + j) >> 5], bit);
+      clash = (old & bit) != 0;
+    }
+    const bool any_clash = __any(clash);
+    if (act && j < i0) atomicAnd(&seen[(s0 + j) >> 5], ~(1u << ((s0 + j) & 31)));
+    if (!any_clash) {
+      E ai, aj;
+      if (act) {
+        ai = data[s0 + i];
+        aj = data[s0 + j];
+      }
+      if (act) {
+        data[s0 + i] = aj;
+        data[s0 + j] = ai;
+      }
+      continue;
     }
     int candY = -1, tgtLater = -1;
     bool lastForJ = true;
@@ -223,18 +279,19 @@ __device__ __forceinline__ void lds_merge_tail(E* data, uint32_t s0, uint32_t N,
   }
 }
 
-template <typename E, int SCAP, int LMAX, bool IDENT>
-__global__ void __launch_bounds__(kLeafThreads) leaf_kernel(LeafArgs a) {
-  constexpr int NT = kLeafThreads;
+template <typename E, int SCAP, int NT, bool IDENT>
+__global__ void __launch_bounds__(NT, NT == 512 ? 2 : 1) leaf_kernel(LeafArgs a) {
   constexpr int KW = (MergeAux<SCAP>::kWords + NT - 1) / NT;  // words per thread in scans
   constexpr int KS = (SCAP + NT - 1) / NT;                     // slots per thread
+  constexpr int BPT = (SCAP / 4 + kLeafMaxMerges + NT - 1) / NT;  // step blocks per thread
+  static_assert(SCAP * sizeof(E) >= 4 * SCAP, "list heads and links live in the data region");
   __shared__ E data[SCAP];
-  __shared__ LeafAux<SCAP, LMAX> aux;
+  __shared__ MergeAux<SCAP> maux;
   __shared__ uint32_t tmp[20];
   __shared__ uint32_t mP[kLeafMaxMerges];
   __shared__ uint32_t mb[kLeafMaxMerges + 1];
   __shared__ uint32_t mmid[kLeafMaxMerges];
-  __shared__ uint64_t red[16];
+  __shared__ uint64_t red[NT / 64];
 
   const int tid = threadIdx.x;
   const Key key{a.key0, a.key1};
@@ -246,16 +303,41 @@ __global__ void __launch_bounds__(kLeafThreads) leaf_kernel(LeafArgs a) {
   E* out = reinterpret_cast<E*>(a.out);
   uint32_t bits = 0;
 
+  // leaves: tpl threads per leaf
+  const uint32_t nleaf = 1u << Lam;
+  const uint32_t tpl = NT >> Lam;
+  const uint32_t lf = tid / tpl, lt = tid % tpl;
+  const uint64_t u = (sb << Lam) + lf;
+  const uint32_t lb = (uint32_t)(bound(a.n, u, a.c) - base);
+  const uint32_t b = (uint32_t)(bound(a.n, u + 1, a.c) - bound(a.n, u, a.c));
+  uint16_t* head = reinterpret_cast<uint16_t*>(data);
+  uint16_t* link = head + SCAP;
+  for (uint32_t i = tid; i < (cnt + 1) / 2; i += NT) reinterpret_cast<uint32_t*>(head)[i] = 0xFFFFFFFFu;
+  __syncthreads();
+  uint32_t F[BPT][2];
+  leaf_fy_sources<BPT>(head, link, lb, b, (uint32_t)u, lt, tpl, key, &bits, F);
+  (void)nleaf;
+
   for (uint32_t i = tid; i < cnt; i += NT) data[i] = IDENT ? ident_value<E>(base + i) : in[base + i];
   __syncthreads();
-
-  // leaves
-  const uint32_t nleaf = 1u << Lam;
-  for (uint32_t lf = 0; lf < nleaf; ++lf) {
-    const uint64_t u = (sb << Lam) + lf;
-    const uint32_t lb = (uint32_t)(bound(a.n, u, a.c) - base);
-    const uint32_t b = (uint32_t)(bound(a.n, u + 1, a.c) - bound(a.n, u, a.c));
-    leaf_fisher_yates<E, LMAX>(data, aux.fy, lb, b, (uint32_t)u, key, &bits);
+  {
+    E val[BPT][4];
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+      const uint32_t g = lt + tpl * k;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (4 * g + e < b) val[k][e] = data[lb + get16(F[k][e >> 1], e & 1)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+      const uint32_t g = lt + tpl * k;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (4 * g + e < b) data[lb + 4 * g + e] = val[k][e];
+    }
+    __syncthreads();
   }
 
   // merge levels inside the super-block
@@ -279,7 +361,7 @@ __global__ void __launch_bounds__(kLeafThreads) leaf_kernel(LeafArgs a) {
       const uint32_t gm = (uint32_t)((sb << (Lam - L)) + mm);
       const W4 f = flip_block(g, gm, L, key);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) aux.mg.words[mm * W + 4 * g + e] = f.w[e];
+      for (int e = 0; e < 4; ++e) maux.words[mm * W + 4 * g + e] = f.w[e];
     }
     __syncthreads();
     // exclusive prefix of zeros over all words (flat)
@@ -289,14 +371,14 @@ __global__ void __launch_bounds__(kLeafThreads) leaf_kernel(LeafArgs a) {
 #pragma unroll
     for (int k = 0; k < KW; ++k) {
       const uint32_t w = tid * KW + k;
-      zloc[k] = w < nw ? 32u - (uint32_t)__popc(aux.mg.words[w]) : 0u;
+      zloc[k] = w < nw ? 32u - (uint32_t)__popc(maux.words[w]) : 0u;
       zs += zloc[k];
     }
     uint32_t run = block_excl_scan<NT>(zs, tmp, nullptr);
 #pragma unroll
     for (int k = 0; k < KW; ++k) {
       const uint32_t w = tid * KW + k;
-      if (w < nw) aux.mg.wpre[w] = run;
+      if (w < nw) maux.wpre[w] = run;
       run += zloc[k];
     }
     __syncthreads();
@@ -306,54 +388,70 @@ __global__ void __launch_bounds__(kLeafThreads) leaf_kernel(LeafArgs a) {
       const uint32_t N = mb[mm + 1] - mb[mm];
       if (32 * wl > N) continue;
       const uint32_t n1 = mmid[mm] - mb[mm], n2 = mb[mm + 1] - mmid[mm];
-      const uint32_t zp = aux.mg.wpre[w] - aux.mg.wpre[mm * W];
+      const uint32_t zp = maux.wpre[w] - maux.wpre[mm * W];
       const uint32_t op = 32 * wl - zp;
-      const uint32_t word = aux.mg.words[w];
+      const uint32_t word = maux.words[w];
       const uint32_t zw = 32u - (uint32_t)__popc(word), ow = (uint32_t)__popc(word);
       if (zp <= n1 && n1 < zp + zw) atomicMin(&mP[mm], (32 * wl + select_zero(word, (int)(n1 - zp))) * 2 + 0);
       if (op <= n2 && n2 < op + ow) atomicMin(&mP[mm], (32 * wl + select_one(word, (int)(n2 - op))) * 2 + 1);
     }
     __syncthreads();
     if (tid < (int)nm) bits += (mP[tid] >> 1) + 1;
-    // stable interleave of A and B into registers, then back
-    E val[KS];
+    // stable interleave of A and B: source slot of every output slot (packed
+    // two per register), then the values into registers, then back.  The
+    // opaque copy of the thread index keeps the compiler from hoisting the
+    // per-slot addresses of every level out of the level loop.
+    uint32_t tv = (uint32_t)tid;
+    asm volatile("" : "+v"(tv));
+    uint32_t SRC[(KS + 1) / 2];
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
-      const uint32_t s = tid + k * NT;
+      const uint32_t s = tv + k * NT;
+      uint32_t src = 0;
       if (s < cnt) {
-        uint32_t lo = 0, hi = nm - 1;
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi + 1) >> 1;
-          if (mb[mid] <= s) lo = mid; else hi = mid - 1;
-        }
-        const uint32_t mm = lo;
+        // merges of a level have sizes within one of each other
+        uint32_t mm = (uint32_t)(((uint64_t)s * nm) / cnt);
+        while (mm > 0 && mb[mm] > s) --mm;
+        while (mm + 1 < nm && mb[mm + 1] <= s) ++mm;
         const uint32_t t = s - mb[mm];
         const uint32_t n1 = mmid[mm] - mb[mm], n2 = mb[mm + 1] - mmid[mm];
         const uint32_t P = mP[mm] >> 1, side = mP[mm] & 1;
-        uint32_t src;
         if (t < P) {
           const uint32_t w = mm * W + (t >> 5);
-          const uint32_t word = aux.mg.words[w];
+          const uint32_t word = maux.words[w];
           const uint32_t bp = t & 31;
-          const uint32_t r0 = aux.mg.wpre[w] - aux.mg.wpre[mm * W] + (uint32_t)__popc(~word & ((1u << bp) - 1u));
+          const uint32_t r0 = maux.wpre[w] - maux.wpre[mm * W] + (uint32_t)__popc(~word & ((1u << bp) - 1u));
           src = ((word >> bp) & 1u) ? n1 + (t - r0) : r0;
         } else {
           src = side == 0 ? t : t - n2;
         }
-        val[k] = data[mb[mm] + src];
+        src += mb[mm];
       }
+      if (k & 1) SRC[k >> 1] |= src << 16;
+      else SRC[k >> 1] = src;
     }
-    __syncthreads();
+    E val[KS];
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
-      const uint32_t s = tid + k * NT;
+      const uint32_t s = tv + k * NT;
+      if (s < cnt) val[k] = data[get16(SRC[k >> 1], k & 1)];
+    }
+    __syncthreads();
+    asm volatile("" : "+v"(tv));
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const uint32_t s = tv + k * NT;
       if (s < cnt) data[s] = val[k];
     }
     __syncthreads();
-    // insertion loops, one wave per merge
+    // insertion loops, one wave per merge; the flip words are dead now and
+    // their space holds the slot bitmap
+    uint32_t* seen = maux.words;
+    for (uint32_t w = tid; w < (cnt + 31) / 32; w += NT) seen[w] = 0u;
+    __syncthreads();
     for (uint32_t mm = tid >> 6; mm < nm; mm += NT / 64) {
       const uint32_t gm = (uint32_t)((sb << (Lam - L)) + mm);
-      lds_merge_tail<E>(data, mb[mm], mb[mm + 1] - mb[mm], mP[mm] >> 1, L, gm, key, &bits);
+      lds_merge_tail<E>(data, seen, mb[mm], mb[mm + 1] - mb[mm], mP[mm] >> 1, L, gm, key, &bits);
     }
     __syncthreads();
   }
@@ -378,6 +476,7 @@ struct PassArgs {
   const uint32_t* P;
   const uint8_t* side;
   uint32_t key0, key1;
+  uint32_t vec_ok;  // base pointer 16-byte aligned
 };
 
 template <typename E>
@@ -396,11 +495,43 @@ __device__ __forceinline__ void store4(E* dst, const E v[4], uint32_t cnt) {
     if (e < cnt) dst[e] = v[e];
 }
 
-template <typename E, int T>
+// Copy the run src[0..cnt) into dst[0..cnt): 16-byte loads for the whole
+// 16-byte groups inside the run when the base pointer allows, element loads
+// for the ragged ends.
+template <typename E, bool VEC>
+__device__ __forceinline__ void stage_run(E* dst, const E* base, uint64_t first, uint32_t cnt) {
+  constexpr uint32_t PER = 16 / sizeof(E) > 0 ? 16 / sizeof(E) : 1;
+  if (!VEC || PER == 1) {
+    for (uint32_t x = threadIdx.x; x < cnt; x += 256) dst[x] = base[first + x];
+    return;
+  }
+  const uint64_t lo = (first + PER - 1) / PER * PER;          // first aligned element
+  const uint64_t hi = (first + cnt) / PER * PER;              // end of the last whole group
+  if (hi <= lo) {
+    for (uint32_t x = threadIdx.x; x < cnt; x += 256) dst[x] = base[first + x];
+    return;
+  }
+  const uint32_t head = (uint32_t)(lo - first);
+  const uint32_t groups = (uint32_t)((hi - lo) / PER);
+  const uint32_t tail0 = (uint32_t)(hi - first);
+  if (threadIdx.x < head) dst[threadIdx.x] = base[first + threadIdx.x];
+  if (threadIdx.x < cnt - tail0) dst[tail0 + threadIdx.x] = base[hi + threadIdx.x];
+  const uint4* g = reinterpret_cast<const uint4*>(base + lo);
+  for (uint32_t q = threadIdx.x; q < groups; q += 256) {
+    const uint4 v = g[q];
+    const E* ve = reinterpret_cast<const E*>(&v);
+#pragma unroll
+    for (uint32_t c = 0; c < PER; ++c) dst[head + q * PER + c] = ve[c];
+  }
+}
+
+// MODE 0: stage the A and B runs of the tile through LDS with element loads;
+// MODE 1: the same with 16-byte loads; MODE 2: gather straight from HBM.
+template <typename E, int T, int MODE>
 __global__ void __launch_bounds__(256) merge_pass_kernel(PassArgs a) {
   constexpr int NW = T / 32;
   static_assert(NW <= 256, "one word per thread");
-  __shared__ E stage[T];
+  __shared__ E stage[MODE == 2 ? 1 : T];
   __shared__ uint32_t Wd[NW];
   __shared__ uint32_t Zw[NW];
   __shared__ uint32_t tmp[8];
@@ -431,8 +562,15 @@ __global__ void __launch_bounds__(256) merge_pass_kernel(PassArgs a) {
   const uint32_t cntA = a1 - a0, cntB = b1 - b0;
   const E* in = reinterpret_cast<const E*>(a.in);
   E* out = reinterpret_cast<E*>(a.out);
-  for (uint32_t x = tid; x < cntA; x += 256) stage[x] = in[s + a0 + x];
-  for (uint32_t x = tid; x < cntB; x += 256) stage[cntA + x] = in[s + n1 + b0 + x];
+  if (MODE != 2) {
+    if (MODE == 1 && a.vec_ok) {
+      stage_run<E, true>(stage, in, s + a0, cntA);
+      stage_run<E, true>(stage + cntA, in, s + n1 + b0, cntB);
+    } else {
+      stage_run<E, false>(stage, in, s + a0, cntA);
+      stage_run<E, false>(stage + cntA, in, s + n1 + b0, cntB);
+    }
+  }
   const uint32_t nblk = (len + 127) / 128;
   if ((uint32_t)tid < nblk) {
     const W4 f = flip_block((t0 >> kGranLog) + tid, m, a.L, Key{a.key0, a.key1});
@@ -445,6 +583,8 @@ __global__ void __launch_bounds__(256) merge_pass_kernel(PassArgs a) {
   const uint32_t zx = block_excl_scan<256>(z, tmp, nullptr);
   if ((uint32_t)tid < NW) Zw[tid] = zx;
   __syncthreads();
+  const E* inA = in + s + a0;
+  const E* inB = in + s + n1 + b0;
   for (uint32_t o = 4 * tid; o < len; o += 1024) {
     const uint32_t wi = o >> 5;
     const uint32_t word = Wd[wi];
@@ -456,13 +596,21 @@ __global__ void __launch_bounds__(256) merge_pass_kernel(PassArgs a) {
       if (k < cnt) {
         const uint32_t tt = o + k;
         const uint32_t t = t0 + tt;
+        uint32_t ia, ib;
+        bool fromB;
         if (t < P) {
           const uint32_t bp = tt & 31;
           const uint32_t zz = zb + (uint32_t)__popc(~word & ((1u << bp) - 1u));
-          v[k] = ((word >> bp) & 1u) ? stage[cntA + tt - zz] : stage[zz];
+          fromB = (word >> bp) & 1u;
+          ia = zz;
+          ib = tt - zz;
         } else {
-          v[k] = side == 0 ? stage[cntA + (t - n1 - b0)] : stage[t - n2 - a0];
+          fromB = side == 0;
+          ia = t - n2 - a0;
+          ib = t - n1 - b0;
         }
+        if (MODE == 2) v[k] = fromB ? inB[ib] : inA[ia];
+        else v[k] = fromB ? stage[cntA + ib] : stage[ia];
       }
     }
     store4<E>(out + s + t0 + o, v, cnt);
@@ -504,31 +652,93 @@ __global__ void __launch_bounds__(256) patch_kernel(PlanArgs pa, int l, const vo
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-template <typename E, int SCAP, bool IDENT>
+template <typename E, int SCAP, int NT, bool IDENT>
 static void launch_leaf_t(const LeafArgs& a, uint64_t grid, hipStream_t st) {
-  hipLaunchKernelGGL((leaf_kernel<E, SCAP, 4097, IDENT>), dim3((uint32_t)grid), dim3(kLeafThreads), 0, st, a);
+  hipLaunchKernelGGL((leaf_kernel<E, SCAP, NT, IDENT>), dim3((uint32_t)grid), dim3(NT), 0, st, a);
 }
 
-int leaf_capacity(uint32_t eb) { return eb == 4 ? 32768 : eb == 8 ? 16384 : 8192; }
+// Super-block size: 128 KiB of elements with 1024 threads (one workgroup per
+// CU), or 64 KiB with 512 threads (two per CU).  MS_LEAF_SMALL=1 picks the
+// latter (a tuning knob; the permutation does not depend on it).
+static bool leaf_small() {
+  static bool v = [] {
+    const char* e = getenv("MS_LEAF_SMALL");
+    return e && atoi(e) != 0;
+  }();
+  return v;
+}
+
+int leaf_capacity(uint32_t eb) {
+  const int big = eb == 4 ? 32768 : eb == 8 ? 16384 : 8192;
+  return leaf_small() ? big / 2 : big;
+}
 int leaf_max_block() { return 4097; }
 int leaf_max_levels() { return 6; }
-int pass_tile(uint32_t eb) { return eb == 4 ? 8192 : eb == 8 ? 4096 : 2048; }
 
 void launch_leaf(const LeafArgs& a, uint32_t eb, bool ident, uint64_t grid, hipStream_t st) {
+  const bool sm = leaf_small();
   if (eb == 4) {
-    if (ident) launch_leaf_t<uint32_t, 32768, true>(a, grid, st);
-    else launch_leaf_t<uint32_t, 32768, false>(a, grid, st);
+    if (ident) {
+      if (sm) launch_leaf_t<uint32_t, 16384, 512, true>(a, grid, st);
+      else launch_leaf_t<uint32_t, 32768, 1024, true>(a, grid, st);
+    } else {
+      if (sm) launch_leaf_t<uint32_t, 16384, 512, false>(a, grid, st);
+      else launch_leaf_t<uint32_t, 32768, 1024, false>(a, grid, st);
+    }
   } else if (eb == 8) {
-    launch_leaf_t<uint64_t, 16384, false>(a, grid, st);
+    if (sm) launch_leaf_t<uint64_t, 8192, 512, false>(a, grid, st);
+    else launch_leaf_t<uint64_t, 16384, 1024, false>(a, grid, st);
   } else {
-    launch_leaf_t<uint4, 8192, false>(a, grid, st);
+    if (sm) launch_leaf_t<uint4, 4096, 512, false>(a, grid, st);
+    else launch_leaf_t<uint4, 8192, 1024, false>(a, grid, st);
   }
 }
 
+// Merge-pass variants: (tile, mode).  The default is variant 0 of each
+// element size; the others are kept for tuning (MS_PASS_VARIANT).
+struct PassVariant {
+  int tile;
+  int mode;
+};
+static const PassVariant kPassVariants[] = {{4096, 1}, {8192, 1}, {2048, 1}, {8192, 0}, {4096, 2}, {2048, 2}};
+
+int pass_variant() {
+  static int v = [] {
+    const char* e = getenv("MS_PASS_VARIANT");
+    int x = e ? atoi(e) : 0;
+    return (x >= 0 && x < (int)(sizeof kPassVariants / sizeof kPassVariants[0])) ? x : 0;
+  }();
+  return v;
+}
+
+int pass_tile(uint32_t eb) {
+  const int t = kPassVariants[pass_variant()].tile;
+  return eb == 4 ? t : eb == 8 ? t / 2 : t / 4;
+}
+
+template <typename E, int T>
+static void launch_pass_t(const PassArgs& a, int mode, uint64_t grid, hipStream_t st) {
+  if (mode == 0) hipLaunchKernelGGL((merge_pass_kernel<E, T, 0>), dim3((uint32_t)grid), dim3(256), 0, st, a);
+  else if (mode == 1) hipLaunchKernelGGL((merge_pass_kernel<E, T, 1>), dim3((uint32_t)grid), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((merge_pass_kernel<E, T, 2>), dim3((uint32_t)grid), dim3(256), 0, st, a);
+}
+
 void launch_merge_pass(const PassArgs& a, uint32_t eb, uint64_t grid, hipStream_t st) {
-  if (eb == 4) hipLaunchKernelGGL((merge_pass_kernel<uint32_t, 8192>), dim3((uint32_t)grid), dim3(256), 0, st, a);
-  else if (eb == 8) hipLaunchKernelGGL((merge_pass_kernel<uint64_t, 4096>), dim3((uint32_t)grid), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((merge_pass_kernel<uint4, 2048>), dim3((uint32_t)grid), dim3(256), 0, st, a);
+  const PassVariant v = kPassVariants[pass_variant()];
+  const int t = pass_tile(eb);
+  if (eb == 4) {
+    if (t == 8192) launch_pass_t<uint32_t, 8192>(a, v.mode, grid, st);
+    else if (t == 4096) launch_pass_t<uint32_t, 4096>(a, v.mode, grid, st);
+    else launch_pass_t<uint32_t, 2048>(a, v.mode, grid, st);
+  } else if (eb == 8) {
+    if (t == 4096) launch_pass_t<uint64_t, 4096>(a, v.mode, grid, st);
+    else if (t == 2048) launch_pass_t<uint64_t, 2048>(a, v.mode, grid, st);
+    else launch_pass_t<uint64_t, 1024>(a, v.mode, grid, st);
+  } else {
+    if (t == 2048) launch_pass_t<uint4, 2048>(a, v.mode, grid, st);
+    else if (t == 1024) launch_pass_t<uint4, 1024>(a, v.mode, grid, st);
+    else launch_pass_t<uint4, 512>(a, v.mode, grid, st);
+  }
 }
 
 void launch_patch(const PlanArgs& pa, int l, const void* in, void* out, uint32_t eb, hipStream_t st) {

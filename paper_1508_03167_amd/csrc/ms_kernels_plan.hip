@@ -177,7 +177,9 @@ __device__ __forceinline__ uint32_t tail_draw(const PlanArgs& pa, uint32_t L, ui
                                               uint32_t* bits) {
   const Key key{pa.key0, pa.key1};
   const W4 db = draw_block(i >> 2, m, L, key);
-  return fdr_draw((uint64_t)i + 1, db.w[i & 3], L, m, i, key, bits);
+  const Draw r = fdr_draw((uint64_t)i + 1, pick(db, i & 3), L, m, i, key);
+  *bits += r.bits;
+  return r.v;
 }
 
 struct TailWg {
@@ -330,7 +332,7 @@ __device__ __forceinline__ uint32_t c0_offset(const PlanArgs& pa, const HbmLevel
   const uint32_t wsel = (src >> 5) & 3;
   uint32_t z = pa.zc[cglob] + pa.zloc[(cglob << kChunkGranLog) + (gi & 255)];
   for (uint32_t w = 0; w < wsel; ++w) z += 32u - (uint32_t)__popc(f.w[w]);
-  const uint32_t word = f.w[wsel];
+  const uint32_t word = pick(f, wsel);
   const uint32_t bit = src & 31;
   z += (uint32_t)__popc(~word & ((1u << bit) - 1u));
   return ((word >> bit) & 1u) ? g.n1 + (src - z) : z;

@@ -1,0 +1,83 @@
+"""GPU parity at the benchmark sizes, in the launch configuration bench.py times.
+
+The oracle's results at these sizes are stored in tests/golden/configs.json
+(written by tests/golden/make_golden.py from the oracle alone): the random-bit
+count, two order-sensitive fingerprints of the whole permutation and 512
+sampled slots.  The GPU side computes the same fingerprints on the device.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import hashing
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _golden(name):
+    return json.load(open(os.path.join(HERE, "golden", "configs.json")))[name]
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    import paper_1508_03167_amd as M
+
+    M.lib()
+    return M
+
+
+def test_permutation_n2p30_seed7(M):
+    import torch
+
+    g = _golden("perm_n2^30_seed7")
+    print(f"[gpu] full-size permutation n={g['n']} seed={g['seed']}", flush=True)
+    out = torch.empty(g["n"], dtype=torch.int32, device="cuda")
+    bits = torch.zeros(1, dtype=torch.int64, device="cuda")
+    M.permutation(out, g["seed"], bits=bits)
+    torch.cuda.synchronize()
+    assert M.device_status() == 0
+    assert int(bits.item()) == g["bits"]
+    pos = torch.tensor([p for p, _ in g["samples"]], dtype=torch.int64, device="cuda")
+    got = (out[pos].to(torch.int64) & 0xFFFFFFFF).cpu().numpy()
+    assert got.tolist() == [v for _, v in g["samples"]]
+    assert list(hashing.fingerprint_torch(out)) == g["fingerprint"]
+    # shuffling the identity in place gives the same array
+    x = torch.arange(g["n"], dtype=torch.int32, device="cuda")
+    M.shuffle_(x, g["seed"])
+    assert torch.equal(x, out)
+    del out, x
+    M.release()
+    torch.cuda.empty_cache()
+
+
+def test_records16_n2p27_seed11(M):
+    import torch
+
+    from paper_1508_03167_amd.inputs import records16
+
+    g = _golden("perm_n2^27_seed11")
+    print(f"[gpu] full-size records n={g['n']} seed={g['seed']}", flush=True)
+    host = records16(g["n"], g["seed"])
+    rec = torch.from_numpy(host.view(np.int64)).cuda()
+    keys0 = rec[:, 0].clone()
+    bits = torch.zeros(1, dtype=torch.int64, device="cuda")
+    M.shuffle_(rec, g["seed"], bits=bits)
+    torch.cuda.synchronize()
+    assert M.device_status() == 0
+    assert int(bits.item()) == g["bits"]
+    payload = rec[:, 1]
+    assert list(hashing.fingerprint_torch(payload)) == g["fingerprint"]
+    pos = torch.tensor([p for p, _ in g["samples"]], dtype=torch.int64, device="cuda")
+    assert payload[pos].cpu().numpy().tolist() == [v for _, v in g["samples"]]
+    assert torch.equal(rec[:, 0], keys0[payload])
+    del rec, keys0, payload
+    M.release()
+    torch.cuda.empty_cache()
