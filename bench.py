@@ -4,14 +4,16 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--n-log2 30] [--no-cpu-base
 
 A step is one complete shuffle of the resident 4 GiB array: the plan, the
 leaf kernel (Fisher-Yates of every leaf plus the merge levels that fit in
-LDS) and every HBM merge pass with its insertion-loop patch.  The JSON line
-carries the whole-job throughput (Gelem/s), the roofline of the kernel class
-that takes most of the step (measured with HIP events around each launch on
-the library's stream), and the CPU oracle timed on a bounded sample.
+LDS) and the HBM merge passes (each runs up to three merge levels, their
+insertion loops included).  The JSON line carries the whole-job throughput
+(Gelem/s), the roofline of the kernel class that takes most of the step
+(measured with HIP events around each launch on the library's stream), and
+the CPU oracle timed on a bounded sample.
 
 Roofline figures:
   * merge pass (HBM-bound): algorithmic bytes per launch = 2 * n * 4 (every
-    element read once and written once), against 8 TB/s;
+    element read once and written once, however many levels the pass runs),
+    against 8 TB/s;
   * leaf kernel (ALU-bound): algorithmic integer ops per element = the
     Philox-4x32-10 work of the bits it draws (one 100-op block per 4 leaf
     draws and per 128 coin flips of each LDS level) plus about 10 ops per
@@ -35,7 +37,7 @@ FDR_OPS = 10.0
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("ms_kernels_data.hip", "ms_device.hpp", "ms_plan.hpp"):
+    for f in ("ms_kernels_data.hip", "ms_kernels_group.hip", "ms_device.hpp", "ms_plan.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1508_03167_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -124,8 +126,9 @@ def main():
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": traffic_from_profiles("merge_pass_n2^30_u32"),
-                "kernel": "merge_pass_kernel<uint32_t,4096,1>", "avg_launch_ms": round(avg, 4),
-                "launches": cnt_cls["merge_pass"], "alg_bytes_per_launch": 2 * n * 4}
+                "kernel": "group_kernel<uint32_t,2048,levels>", "avg_launch_ms": round(avg, 4),
+                "launches": cnt_cls["merge_pass"], "levels_per_launch": round(plan["hbm_levels"] / launches, 3),
+                "alg_bytes_per_launch": 2 * n * 4}
 
     def leaf_roof():
         launches = max(cnt_cls["leaf"], 1)
@@ -134,7 +137,7 @@ def main():
         ach = ops_per_elem * n / (avg / 1e3) / 1e9
         return {"bound": "alu", "achieved": round(ach, 1), "peak": ALU_PEAK_GOPS, "unit": "Gop/s",
                 "frac": round(ach / ALU_PEAK_GOPS, 4), "traffic": traffic_from_profiles("leaf_n2^30_u32"),
-                "kernel": "leaf_kernel<uint32_t,32768,1024>", "avg_launch_ms": round(avg, 4),
+                "kernel": "leaf_kernel<uint32_t,16384,512>", "avg_launch_ms": round(avg, 4),
                 "launches": cnt_cls["leaf"], "alg_ops_per_launch": ops_per_elem * n,
                 "alg_bytes_per_launch": 2 * n * 4}
 
@@ -158,7 +161,8 @@ def main():
         "config": {"workload": f"MergeShuffle of one uint32 identity array, n=2^{args.n_log2}, seed {args.seed}, "
                                f"cutoff 4096, resident in HBM",
                    "n": n, "levels": plan["levels"], "lds_levels": plan["lds_levels"],
-                   "hbm_passes": plan["hbm_levels"], "parallelism": "single GPU"},
+                   "hbm_levels": plan["hbm_levels"], "hbm_passes": cnt_cls["merge_pass"] // args.steps,
+                   "parallelism": "single GPU"},
         "roofline": dict(roofs[dominant], dominant_kernel_class=dominant),
         "roofline_other": roofs["leaf" if dominant == "merge_pass" else "merge_pass"],
         "ms_per_step_by_kernel_class": breakdown,

@@ -74,8 +74,11 @@ enum {
  * leaf_B changes the permutation (it is the paper's cutoff); the others never do. */
 typedef struct ms_config {
   uint32_t leaf_B;          /* cutoff: leaves hold at most leaf_B+1 elements; 0 = 4096; at most 4096 */
-  uint32_t levels_per_pass; /* HBM merge levels fused per pass; 0 = default; clamped to the
-                               supported maximum (currently 1) */
+  uint32_t levels_per_pass; /* HBM merge levels fused into one pass over the array (each
+                               workgroup runs a tile of the top level and, below it, the
+                               windows of the lower levels that feed it); 0 = default (3);
+                               clamped to 1..3; the passes split the levels as evenly as
+                               possible */
   uint32_t lds_levels_max;  /* cap on merge levels run in LDS by the leaf kernel; 0 = as many as fit */
   uint32_t flags;           /* MS_CFG_HBM_ONLY: run every merge level as an HBM pass */
 } ms_config;

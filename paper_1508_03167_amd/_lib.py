@@ -107,24 +107,26 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def shuffle_(t, seed: int, *, stream=None, bits=None, leaf_B=0, lds_levels_max=0, hbm_only=False):
+def shuffle_(t, seed: int, *, stream=None, bits=None, leaf_B=0, lds_levels_max=0, hbm_only=False,
+             levels_per_pass=0):
     """Shuffle the contiguous device tensor t in place along its first dimension
     (row size 4, 8 or 16 bytes).  bits: optional int64 device tensor, += bits used."""
     assert t.is_cuda and t.is_contiguous()
     eb = t.element_size() * (t[0].numel() if t.dim() > 1 else 1)
     n = t.shape[0]
     rc = lib().ms_shuffle_ex(_ptr(t), n, eb, seed & (2**64 - 1), _stream(stream),
-                             _cfg(leaf_B, lds_levels_max, hbm_only),
+                             _cfg(leaf_B, lds_levels_max, hbm_only, levels_per_pass),
                              ctypes.c_void_p(bits.data_ptr()) if bits is not None else None)
     _check(rc)
     return t
 
 
-def permutation(out, seed: int, *, stream=None, bits=None, leaf_B=0, lds_levels_max=0, hbm_only=False):
+def permutation(out, seed: int, *, stream=None, bits=None, leaf_B=0, lds_levels_max=0, hbm_only=False,
+                levels_per_pass=0):
     """Write MergeShuffle's permutation of 0..n-1 into the int32/uint32 device tensor out."""
     assert out.is_cuda and out.is_contiguous() and out.element_size() == 4
     rc = lib().ms_permutation_ex(_ptr(out), out.numel(), seed & (2**64 - 1), _stream(stream),
-                                 _cfg(leaf_B, lds_levels_max, hbm_only),
+                                 _cfg(leaf_B, lds_levels_max, hbm_only, levels_per_pass),
                                  ctypes.c_void_p(bits.data_ptr()) if bits is not None else None)
     _check(rc)
     return out
@@ -143,9 +145,10 @@ def shuffle_batched_(tensors, seed: int, *, stream=None, bits=None, leaf_B=0):
     return tensors
 
 
-def plan(n: int, elem_bytes: int = 4, leaf_B=0, lds_levels_max=0, hbm_only=False) -> dict:
+def plan(n: int, elem_bytes: int = 4, leaf_B=0, lds_levels_max=0, hbm_only=False, levels_per_pass=0) -> dict:
     info = MSPlanInfo()
-    _check(lib().ms_plan(n, elem_bytes, _cfg(leaf_B, lds_levels_max, hbm_only), ctypes.byref(info)))
+    _check(lib().ms_plan(n, elem_bytes, _cfg(leaf_B, lds_levels_max, hbm_only, levels_per_pass),
+                         ctypes.byref(info)))
     return {f: getattr(info, f) for f, _ in MSPlanInfo._fields_}
 
 

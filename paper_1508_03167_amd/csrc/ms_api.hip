@@ -22,29 +22,8 @@
 #include "ms_plan.hpp"
 
 namespace ms {
-struct LeafArgs {
-  const void* in;
-  void* out;
-  uint64_t n;
-  uint32_t c;
-  uint32_t lds_levels;
-  uint32_t key0, key1;
-  unsigned long long* bits;
-};
-struct PassArgs {
-  const void* in;
-  void* out;
-  uint64_t n;
-  uint32_t c, L, tpm, cpm;
-  uint64_t chunk_base;
-  uint64_t merge_base;
-  const uint16_t* zloc;
-  const uint32_t* zc;
-  const uint32_t* P;
-  const uint8_t* side;
-  uint32_t key0, key1;
-  uint32_t vec_ok;
-};
+void launch_group(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st);
+int group_tile(uint32_t eb);
 void launch_plan(const PlanArgs& pa, hipStream_t st);
 void launch_leaf(const LeafArgs& a, uint32_t eb, bool ident, uint64_t grid, hipStream_t st);
 void launch_merge_pass(const PassArgs& a, uint32_t eb, uint64_t grid, hipStream_t st);
@@ -84,7 +63,8 @@ constexpr uint32_t kDefaultB = 4096;
 // planner
 // ---------------------------------------------------------------------------
 struct Layout {
-  size_t zloc, ctot, zc, P, side, kcnt, toff, tail_src, bcnt, bfill, boff, part, pool_x, pool_step, pool_src;
+  size_t zloc, ctot, zc, P, side, kcnt, toff, tail_src, bcnt, bfill, boff, part, pool_x, pool_step, pool_src,
+      tail_xsrc, pool_xsrc, bnd;
   size_t bytes;
 };
 
@@ -93,6 +73,10 @@ struct HostPlan {
   uint32_t eb = 4, B = kDefaultB, c = 0, lam = 0, nlev = 0;
   uint64_t q = 1;
   uint64_t pass_tiles = 0;
+  bool fused = true;              // HBM levels run as fused groups (else one pass + patch per level)
+  uint32_t ngroup = 0;
+  uint32_t gfirst[kMaxLevels];    // first HBM level index of each group
+  uint32_t glam[kMaxLevels];      // levels in each group
   PlanArgs pa;
   Layout lay;
 };
@@ -140,7 +124,12 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
     const uint64_t nmax = ceil_shift(n, c - L);
     lv.nmax = (uint32_t)nmax;
     lv.cpm = (uint32_t)ceil_shift(nmax + 1, kChunkLog);
-    lv.bpm = (uint32_t)ceil_shift(nmax, kBucketLog);
+    {
+      uint32_t bl = 5;
+      while (bl < 24 && (double)(1u << (bl + 1)) <= 2.5 * std::sqrt((double)nmax)) ++bl;
+      lv.blog = bl;
+    }
+    lv.bpm = (uint32_t)ceil_shift(nmax, lv.blog);
     lv.tpm = (uint32_t)((nmax + T - 1) / T);
     const double ek = 0.8 * std::sqrt((double)nmax);
     lv.wpm = (uint32_t)std::max(1.0, std::ceil(ek / 1024.0));
@@ -153,7 +142,6 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
     double bnd = 1.2 * (double)lv.nmerge * std::sqrt((double)nmax) + 14.0 * std::sqrt((double)n) + 64.0;
     uint64_t lcap = (uint64_t)std::ceil(bnd);
     if (lcap > n) lcap = n;
-    lv.pool_cap = lcap;
     chunks += (uint64_t)lv.nmerge * lv.cpm;
     merges += lv.nmerge;
     buckets += (uint64_t)lv.nmerge * lv.bpm;
@@ -161,6 +149,49 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
     cap += lcap;
     tiles = std::max<uint64_t>(tiles, (uint64_t)lv.nmerge * lv.tpm);
   }
+  // fused passes: groups of at most 3 consecutive HBM levels, sizes within one
+  uint32_t lpp = cfg && cfg->levels_per_pass ? cfg->levels_per_pass : 3u;
+  if (lpp > 3) lpp = 3;
+  static const bool old_pass = [] {
+    const char* e = getenv("MS_OLD_PASS");
+    return e && atoi(e) != 0;
+  }();
+  hp.fused = !old_pass;
+  if (!hp.fused) lpp = 1;
+  hp.ngroup = hp.nlev ? (hp.nlev + lpp - 1) / lpp : 0;
+  {
+    uint32_t l = 0;
+    for (uint32_t g = 0; g < hp.ngroup; ++g) {
+      const uint32_t sz = hp.nlev / hp.ngroup + (g < hp.nlev % hp.ngroup ? 1u : 0u);
+      hp.gfirst[g] = l;
+      hp.glam[g] = sz;
+      for (uint32_t k = 0; k < sz; ++k) pa.lev[l + k].group_bottom = k == 0 ? 1u : 0u;
+      l += sz;
+    }
+  }
+  uint64_t all_bnd = 0;
+  if (hp.fused) {
+    const uint32_t Tg = (uint32_t)group_tile(eb);
+    tiles = 0;
+    for (uint32_t g = 0; g < hp.ngroup; ++g) {
+      const HbmLevel& top = pa.lev[hp.gfirst[g] + hp.glam[g] - 1];
+      GroupInfo& gi = pa.grp[g];
+      gi.lf = hp.gfirst[g];
+      gi.lam = hp.glam[g];
+      gi.T = Tg;
+      gi.tpm = (top.nmax + Tg - 1) / Tg;
+      gi.bnd_first = all_bnd;
+      for (uint32_t k = 0; k < gi.lam; ++k) {
+        pa.lev[gi.lf + k].grp = g;
+        pa.lev[gi.lf + k].gli = k;
+      }
+      const uint64_t t = (uint64_t)top.nmerge * gi.tpm;
+      all_bnd += (uint64_t)top.nmerge * (gi.tpm + 1);
+      tiles = std::max<uint64_t>(tiles, t);
+    }
+    pa.ngroup = hp.ngroup;
+  }
+  pa.total_bnd = all_bnd;
   pa.total_chunks = chunks;
   pa.total_merges = merges;
   pa.total_buckets = buckets;
@@ -186,6 +217,9 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
   y.pool_x = take(cap * 4);
   y.pool_step = take(cap * 4);
   y.pool_src = take(cap * 4);
+  y.tail_xsrc = hp.fused ? take(cap * 4) : 0;
+  y.pool_xsrc = hp.fused ? take(cap * 4) : 0;
+  y.bnd = hp.fused ? take(all_bnd * kBndStride * 4) : 0;
   y.bytes = hp.nlev ? o : 0;
   return MS_OK;
 }
@@ -307,12 +341,16 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
     pa.pool_x = reinterpret_cast<uint32_t*>(b + y.pool_x);
     pa.pool_step = reinterpret_cast<uint32_t*>(b + y.pool_step);
     pa.pool_src = reinterpret_cast<uint32_t*>(b + y.pool_src);
+    pa.tail_xsrc = hp.fused ? reinterpret_cast<uint32_t*>(b + y.tail_xsrc) : nullptr;
+    pa.pool_xsrc = hp.fused ? reinterpret_cast<uint32_t*>(b + y.pool_xsrc) : nullptr;
+    pa.bnd = hp.fused ? reinterpret_cast<uint32_t*>(b + y.bnd) : nullptr;
     ProfScope ps(0, st);
     launch_plan(pa, st);
   }
   void* X = ptr;
   void* Y = ar.data;
-  void* cur = (hp.nlev % 2 == 0) ? X : Y;
+  const uint32_t npass = hp.fused ? hp.ngroup : hp.nlev;
+  void* cur = (npass % 2 == 0) ? X : Y;
   {
     LeafArgs la;
     la.in = X;
@@ -326,7 +364,46 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
     ProfScope ps(1, st);
     launch_leaf(la, eb, ident, hp.q >> hp.lam, st);
   }
-  for (uint32_t l = 0; l < hp.nlev; ++l) {
+  for (uint32_t g = 0; hp.fused && g < hp.ngroup; ++g) {
+    void* other = cur == X ? Y : X;
+    GroupArgs ga;
+    memset(&ga, 0, sizeof ga);
+    const GroupInfo& gi = pa.grp[g];
+    ga.X = cur;
+    ga.Z = other;
+    ga.n = n;
+    ga.c = hp.c;
+    ga.tpm = gi.tpm;
+    ga.ntiles = (uint32_t)((uint64_t)pa.lev[gi.lf + gi.lam - 1].nmerge * gi.tpm);
+    ga.key0 = pa.key0;
+    ga.key1 = pa.key1;
+    ga.vec_ok = ((uintptr_t)cur % 16 == 0 && (uintptr_t)other % 16 == 0) ? 1u : 0u;
+    ga.P = pa.P;
+    ga.side = pa.side;
+    ga.bnd = pa.bnd + gi.bnd_first * kBndStride;
+    ga.toff = pa.toff;
+    ga.tail_xsrc = pa.tail_xsrc;
+    ga.boff = pa.boff;
+    ga.pool_x = pa.pool_x;
+    ga.pool_xsrc = pa.pool_xsrc;
+    ga.tail_cap = pa.tail_cap;
+    ga.pool_cap = pa.pool_cap;
+    for (uint32_t k = 0; k < gi.lam; ++k) {
+      const HbmLevel& lv = pa.lev[gi.lf + k];
+      ga.L[k] = lv.L;
+      ga.blog[k] = lv.blog;
+      ga.bpm[k] = lv.bpm;
+      ga.merge_base[k] = lv.merge_base;
+      ga.bucket_base[k] = lv.bucket_base;
+    }
+    const HbmLevel& top = pa.lev[gi.lf + gi.lam - 1];
+    {
+      ProfScope ps(2, st);
+      launch_group(ga, (int)gi.lam, eb, (uint64_t)top.nmerge * gi.tpm, st);
+    }
+    cur = other;
+  }
+  for (uint32_t l = 0; !hp.fused && l < hp.nlev; ++l) {
     void* other = cur == X ? Y : X;
     const HbmLevel& lv = pa.lev[l];
     PassArgs a;

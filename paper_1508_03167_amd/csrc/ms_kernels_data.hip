@@ -32,15 +32,6 @@ namespace ms {
 
 constexpr int kLeafMaxMerges = 64;  // at most 2^6 leaves per super-block
 
-struct LeafArgs {
-  const void* in;
-  void* out;
-  uint64_t n;
-  uint32_t c;
-  uint32_t lds_levels;
-  uint32_t key0, key1;
-  unsigned long long* bits;
-};
 
 template <typename E>
 __device__ __forceinline__ E ident_value(uint64_t i);
@@ -106,10 +97,35 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
           jj[e] = dr.v;
         }
       }
+      // push r onto the list of slot j_r: the four swaps of a block go out
+      // together and only the rare lost races retry
+      uint32_t cur[4];
+      bool todo[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const uint32_t r = 4 * g + e;
-        if (jj[e] != NONE) link[lb + r] = (uint16_t)xchg_u16(head, lb + jj[e], r);
+        todo[e] = jj[e] != NONE;
+        cur[e] = todo[e] ? reinterpret_cast<uint32_t*>(head)[(lb + jj[e]) >> 1] : 0u;
+      }
+      for (;;) {
+        bool any = false;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (todo[e]) {
+            const uint32_t pos = lb + jj[e];
+            const uint32_t sh = (pos & 1u) * 16u;
+            const uint32_t r = 4 * g + e;
+            const uint32_t nv = (cur[e] & ~(0xFFFFu << sh)) | (r << sh);
+            const uint32_t prev = atomicCAS(reinterpret_cast<uint32_t*>(head) + (pos >> 1), cur[e], nv);
+            if (prev == cur[e]) {
+              link[lb + r] = (uint16_t)((prev >> sh) & 0xFFFFu);
+              todo[e] = false;
+            } else {
+              cur[e] = prev;
+              any = true;
+            }
+          }
+        }
+        if (!any) break;
       }
       J[k][0] = jj[0] | (jj[1] << 16);
       J[k][1] = jj[2] | (jj[3] << 16);
@@ -168,35 +184,65 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
       if (4 * g + e < b) head[lb + 4 * g + e] = (uint16_t)get16(U[k][e >> 1], e & 1);
   }
   __syncthreads();
-  // 4. F[r] = top(nxt(r)) or j_r; F[0] = top(0); top() follows up() to its end
+  // 4. top() of every slot by pointer jumping over the up() links (each
+  //    round halves the remaining chain), then F[r] = top(nxt(r)) or j_r,
+  //    F[0] = top(0)
+  for (;;) {
+    uint32_t nt[BPT][2];
+    bool changed = false;
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+      const uint32_t g = lt + tpl * k;
+      nt[k][0] = nt[k][1] = 0u;
+      if (4 * g < b) {
+        uint32_t v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t x = 4 * g + e;
+          v[e] = NONE;
+          if (x < b) {
+            const uint32_t t = head[lb + x];
+            if (t != NONE) {
+              const uint32_t tt = head[lb + t];
+              v[e] = tt != NONE ? tt : t;
+              changed |= tt != NONE;
+            }
+          }
+        }
+        nt[k][0] = (v[0] & 0xFFFFu) | (v[1] << 16);
+        nt[k][1] = (v[2] & 0xFFFFu) | (v[3] << 16);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+      const uint32_t g = lt + tpl * k;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (4 * g + e < b) head[lb + 4 * g + e] = (uint16_t)get16(nt[k][e >> 1], e & 1);
+    }
+    if (!__syncthreads_or(changed)) break;
+  }
+  // head[x] is now the end of x's up() chain, or NONE if x has no up()
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
     const uint32_t g = lt + tpl * k;
     F[k][0] = F[k][1] = 0u;
     if (4 * g < b) {
-      uint32_t t[4];
-      bool walk[4];
+      uint32_t f[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const uint32_t x = 4 * g + e;
         const uint32_t nx = get16(X[k][e >> 1], e & 1);
-        walk[e] = x < b && (x == 0 || nx != NONE);
-        t[e] = x == 0 ? 0u : (nx != NONE ? nx : get16(J[k][e >> 1], e & 1));
-      }
-      for (;;) {
-        bool any = false;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (walk[e]) {
-            const uint32_t up = head[lb + t[e]];
-            if (up != NONE) { t[e] = up; any = true; }
-            else walk[e] = false;
-          }
+        const uint32_t t = x == 0 ? 0u : nx;
+        f[e] = get16(J[k][e >> 1], e & 1);
+        if (x < b && (x == 0 || nx != NONE)) {
+          const uint32_t top = head[lb + t];
+          f[e] = top != NONE ? top : t;
         }
-        if (!any) break;
       }
-      F[k][0] = (t[0] & 0xFFFFu) | (t[1] << 16);
-      F[k][1] = (t[2] & 0xFFFFu) | (t[3] << 16);
+      F[k][0] = (f[0] & 0xFFFFu) | (f[1] << 16);
+      F[k][1] = (f[2] & 0xFFFFu) | (f[3] << 16);
     }
   }
   __syncthreads();
@@ -280,7 +326,8 @@ __device__ __forceinline__ void lds_merge_tail(E* data, uint32_t* seen, uint32_t
 }
 
 template <typename E, int SCAP, int NT, bool IDENT>
-__global__ void __launch_bounds__(NT, NT == 512 ? 2 : 1) leaf_kernel(LeafArgs a) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 4 : 4)))
+leaf_kernel(LeafArgs a) {
   constexpr int KW = (MergeAux<SCAP>::kWords + NT - 1) / NT;  // words per thread in scans
   constexpr int KS = (SCAP + NT - 1) / NT;                     // slots per thread
   constexpr int BPT = (SCAP / 4 + kLeafMaxMerges + NT - 1) / NT;  // step blocks per thread
@@ -403,6 +450,7 @@ __global__ void __launch_bounds__(NT, NT == 512 ? 2 : 1) leaf_kernel(LeafArgs a)
     // per-slot addresses of every level out of the level loop.
     uint32_t tv = (uint32_t)tid;
     asm volatile("" : "+v"(tv));
+    const float inv_msize = (float)nm / (float)cnt;
     uint32_t SRC[(KS + 1) / 2];
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
@@ -410,7 +458,7 @@ __global__ void __launch_bounds__(NT, NT == 512 ? 2 : 1) leaf_kernel(LeafArgs a)
       uint32_t src = 0;
       if (s < cnt) {
         // merges of a level have sizes within one of each other
-        uint32_t mm = (uint32_t)(((uint64_t)s * nm) / cnt);
+        uint32_t mm = min((uint32_t)((float)s * inv_msize), nm - 1);
         while (mm > 0 && mb[mm] > s) --mm;
         while (mm + 1 < nm && mb[mm + 1] <= s) ++mm;
         const uint32_t t = s - mb[mm];
@@ -464,20 +512,6 @@ __global__ void __launch_bounds__(NT, NT == 512 ? 2 : 1) leaf_kernel(LeafArgs a)
 // ---------------------------------------------------------------------------
 // HBM merge pass
 // ---------------------------------------------------------------------------
-struct PassArgs {
-  const void* in;
-  void* out;
-  uint64_t n;
-  uint32_t c, L, tpm, cpm;
-  uint64_t chunk_base;  // global chunk of merge 0 of this level
-  uint64_t merge_base;  // global merge index of merge 0 of this level
-  const uint16_t* zloc;
-  const uint32_t* zc;
-  const uint32_t* P;
-  const uint8_t* side;
-  uint32_t key0, key1;
-  uint32_t vec_ok;  // base pointer 16-byte aligned
-};
 
 template <typename E>
 __device__ __forceinline__ void store4(E* dst, const E v[4], uint32_t cnt) {
@@ -637,7 +671,7 @@ __global__ void __launch_bounds__(256) patch_kernel(PlanArgs pa, int l, const vo
   for (uint32_t d = w * 256 + threadIdx.x; d < k; d += lv.wpm * 256) {
     if (toff + d >= pa.tail_cap) break;
     const uint32_t src = pa.tail_src[toff + d];
-    if (src != kNone32) out[s + P + d] = in[s + src];
+    if (src < N) out[s + P + d] = in[s + src];
   }
   const uint64_t bb = lv.bucket_base + (uint64_t)m * lv.bpm;
   const uint64_t lo = pa.boff[bb];
@@ -645,7 +679,8 @@ __global__ void __launch_bounds__(256) patch_kernel(PlanArgs pa, int l, const vo
   if (hi > pa.pool_cap) hi = pa.pool_cap;
   for (uint64_t e = lo + (uint64_t)w * 256 + threadIdx.x; e < hi; e += (uint64_t)lv.wpm * 256) {
     const uint32_t src = pa.pool_src[e];
-    if (src != kNone32) out[s + pa.pool_x[e]] = in[s + src];
+    const uint32_t x = pa.pool_x[e];
+    if (src < N && x < N) out[s + x] = in[s + src];
   }
 }
 
@@ -657,13 +692,13 @@ static void launch_leaf_t(const LeafArgs& a, uint64_t grid, hipStream_t st) {
   hipLaunchKernelGGL((leaf_kernel<E, SCAP, NT, IDENT>), dim3((uint32_t)grid), dim3(NT), 0, st, a);
 }
 
-// Super-block size: 128 KiB of elements with 1024 threads (one workgroup per
-// CU), or 64 KiB with 512 threads (two per CU).  MS_LEAF_SMALL=1 picks the
-// latter (a tuning knob; the permutation does not depend on it).
+// Super-block size: 64 KiB of elements with 512 threads (two workgroups per
+// CU, the default: measured faster), or 128 KiB with 1024 threads (one per
+// CU, MS_LEAF_BIG=1).  A tuning knob only: the permutation does not depend on it.
 static bool leaf_small() {
   static bool v = [] {
-    const char* e = getenv("MS_LEAF_SMALL");
-    return e && atoi(e) != 0;
+    const char* e = getenv("MS_LEAF_BIG");
+    return !(e && atoi(e) != 0);
   }();
   return v;
 }

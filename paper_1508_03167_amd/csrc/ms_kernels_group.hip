@@ -1,0 +1,403 @@
+// ms_kernels_group.hip -- LAM consecutive HBM merge levels in one pass.
+//
+// A workgroup produces T output slots [t0, t1) of one merge M of the top
+// level of the group.  By the coin-flip loop's stable interleave (Algorithm
+// 2) those slots come from one contiguous window of each half of M's input:
+// [r0(t0), r0(t1)) of the left half and [t0 - r0(t0), t1 - r0(t1)) of the
+// right half, r0(t) counting the zero flips before slot t (slots past the
+// break step P take the side that is left, in order).  Each of these windows
+// is itself the output window of a merge one level down, so the tile defines
+// a binary tree of windows whose 2^LAM leaves are contiguous runs of the pass
+// input.  Laid out in tree order, a window occupies the same LDS range as its
+// two children, so every level is one interleave from one LDS buffer into the
+// other.  The insertion loop's slots of every level inside the tile are then
+// overwritten with their final values, fetched from the pass input at the
+// offsets the plan traced down to it.
+#include <stdlib.h>
+
+#include <algorithm>
+
+#include "ms_device.hpp"
+#include "ms_plan.hpp"
+
+namespace ms {
+
+struct Win {
+  uint32_t m, L, u0, u1, ra0, ra1, off, P, side, n1, n2, g0, wb, toff;
+  uint64_t s;
+};
+
+// Register copy of an element: a native 4 x u32 vector for uint4, whose
+// wrapper type keeps an array of them out of registers.
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+template <typename E> struct RegOf { using type = E; };
+template <> struct RegOf<uint4> { using type = v4u; };
+
+template <typename E, int T, int LAM>
+__global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
+  constexpr int NODES = (1 << LAM) - 1;
+  constexpr int NB = NODES / 2 + 1;  // bottom windows
+  // flip words of every window: at most T/32 + 8 per window and level
+  constexpr int NWORD = LAM * (T / 32) + 8 * NODES + 8 * LAM;
+  constexpr int KW = (NWORD + 255) / 256;
+  constexpr int PT = T / 256;  // staged elements per thread
+  constexpr int PK = 2;        // patches per thread fetched ahead of the levels
+  constexpr uint32_t NONE = 0xFFFFFFFFu;
+  using R = typename RegOf<E>::type;
+  __shared__ __align__(16) E buf[2][T];
+  __shared__ __align__(16) uint32_t words[NWORD];
+  __shared__ uint32_t wpre[NWORD];
+  __shared__ uint32_t tmp[8];
+  __shared__ __align__(16) uint32_t hot[NODES][8];
+  __shared__ Win win[NODES + 1];
+  __shared__ uint32_t rec[2][2 * NODES];  // boundary records at both tile edges
+  __shared__ uint32_t rs[2 * NB + 1];     // LDS start of each staged run (+ end)
+  __shared__ uint32_t rsrc[2 * NB];       // its first element, from the top merge's
+  // insertion-loop slots of the tile: per window, a range of the dense
+  // per-step array (slots >= P) and a range of target entries (its buckets)
+  __shared__ uint32_t pcnt[2 * NODES];
+  __shared__ uint64_t pbase[2 * NODES];
+  const int tid = threadIdx.x;
+  const Key key{a.key0, a.key1};
+  const E* X = reinterpret_cast<const E*>(a.X);
+  const R* XR = reinterpret_cast<const R*>(a.X);
+  E* Z = reinterpret_cast<E*>(a.Z);
+  const uint32_t tile = blockIdx.x;
+  if (tile >= a.ntiles) return;
+  const uint32_t M = tile / a.tpm;
+  const uint32_t b = tile - M * a.tpm;
+
+  // 1. boundary records, and per window the break step, side and first step
+  if (tid < 4 * NODES) {
+    const uint32_t e = tid >= 2 * NODES ? 1u : 0u;
+    const uint32_t w = tid - e * 2 * NODES;
+    rec[e][w] = a.bnd[((uint64_t)M * (a.tpm + 1) + b + e) * kBndStride + w];
+  } else if (tid >= 128 && tid < 128 + NODES) {
+    const int k = tid - 128;
+    const int d = 31 - __clz(k + 1);
+    const int li = LAM - 1 - d;
+    const uint32_t m = (M << d) + (uint32_t)(k - ((1 << d) - 1));
+    const uint64_t gm = a.merge_base[li] + m;
+    win[k].P = a.P[gm];
+    win[k].side = a.side[gm];
+    win[k].toff = a.toff[gm];
+  }
+  __syncthreads();
+  if (rec[0][0] >= rec[1][0]) return;  // the top merge ends before this tile
+
+  // 2. the window tree (one thread per window)
+  if (tid < NODES) {
+    const int k = tid;
+    const int d = 31 - __clz(k + 1);
+    const int li = LAM - 1 - d;
+    const uint32_t idx = (uint32_t)(k - ((1 << d) - 1));
+    Win& w = win[k];
+    w.m = (M << d) + idx;
+    w.L = a.L[li];
+    const uint64_t i0 = (uint64_t)w.m << w.L;
+    const uint64_t s0 = bound(a.n, i0, a.c);
+    const uint64_t mid = bound(a.n, i0 + (1ull << (w.L - 1)), a.c);
+    const uint64_t e0 = bound(a.n, i0 + (1ull << w.L), a.c);
+    w.s = s0;
+    w.n1 = (uint32_t)(mid - s0);
+    w.n2 = (uint32_t)(e0 - mid);
+    const uint32_t u0 = rec[0][2 * k], u1 = rec[1][2 * k];
+    w.u0 = u0;
+    w.u1 = u1;
+    w.ra0 = rec[0][2 * k + 1];
+    w.ra1 = rec[1][2 * k + 1];
+    w.g0 = u0 >> kGranLog;
+    // LDS offset: a right child sits after its left sibling's window
+    uint32_t off = 0, node = 0;
+    for (int j = d; j-- > 0;) {
+      if ((idx >> j) & 1u) {
+        off += rec[1][2 * node + 1] - rec[0][2 * node + 1];
+        node = 2 * node + 2;
+      } else {
+        node = 2 * node + 1;
+      }
+    }
+    w.off = off;
+    // flip words: nodes in breadth-first order, whole granules per window
+    uint32_t wb = 0;
+    for (int j = 0; j < k; ++j) {
+      const uint32_t a0 = rec[0][2 * j], a1 = rec[1][2 * j];
+      wb += a1 > a0 ? 4 * (((a1 + 127) >> kGranLog) - (a0 >> kGranLog)) : 0u;
+    }
+    w.wb = wb;
+    if (k >= NODES / 2) {
+      // a bottom window reads one run of each half of its merge's input
+      const uint32_t j = (uint32_t)(k - NODES / 2);
+      const uint64_t sTop = bound(a.n, (uint64_t)M << a.L[LAM - 1], a.c);
+      const uint32_t rel = (uint32_t)(s0 - sTop);
+      rs[2 * j] = off;
+      rs[2 * j + 1] = off + (w.ra1 - w.ra0);
+      rsrc[2 * j] = rel + w.ra0;
+      rsrc[2 * j + 1] = rel + w.n1 + (u0 - w.ra0);
+      if (k == NODES - 1) rs[2 * j + 2] = rec[1][0] - rec[0][0];
+    }
+    if (k == NODES - 1) win[NODES].wb = wb + (u1 > u0 ? 4 * (((u1 + 127) >> kGranLog) - w.g0) : 0u);
+    // insertion-loop slots: steps max(u0, P) .. u1 - 1, and the target entries
+    // of the buckets that cover [u0, u1)
+    const uint32_t P = w.P;
+    const uint32_t x0 = max(u0, P), x1 = max(u1, P);
+    uint64_t sb = (uint64_t)w.toff + (x0 - P);
+    uint32_t sc = x1 - x0;
+    if (sb >= a.tail_cap) sc = 0;
+    else if (sb + sc > a.tail_cap) sc = (uint32_t)(a.tail_cap - sb);
+    uint64_t plo = 0;
+    uint32_t pc = 0;
+    if (u1 > u0) {
+      const uint64_t bb = a.bucket_base[li] + (uint64_t)w.m * a.bpm[li];
+      plo = a.boff[bb + (u0 >> a.blog[li])];
+      uint64_t phi = a.boff[bb + ((u1 - 1) >> a.blog[li]) + 1];
+      if (phi > a.pool_cap) phi = a.pool_cap;
+      pc = phi > plo ? (uint32_t)(phi - plo) : 0u;
+    }
+    pcnt[k] = sc;
+    pbase[k] = sb;
+    pcnt[NODES + k] = pc;
+    pbase[NODES + k] = plo;
+  }
+  __syncthreads();
+  const uint32_t len = win[0].u1 - win[0].u0;
+  const uint64_t sM = win[0].s;
+
+  // 3. loads: the 2^LAM runs of the pass input, and the first PK * 256
+  //    insertion-loop patches (they land after the flips are counted)
+  R v[PT];
+  {
+    int r = 0;
+    uint32_t si[PT];
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      const uint32_t p = tid + 256 * i;
+      si[i] = 0;
+      if (p < len) {
+        while (p >= rs[r + 1]) ++r;
+        si[i] = rsrc[r] + (p - rs[r]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PT; ++i) v[i] = XR[sM + si[i]];
+  }
+  uint32_t ptot = 0;
+#pragma unroll
+  for (int r = 0; r < 2 * NODES; ++r) ptot += pcnt[r];
+  // patch e of the tile: its level (bits 16..), LDS slot (bits 0..15) and
+  // pass-input offset, or NONE
+  auto patch_at = [&](uint32_t e, uint32_t& meta) -> uint64_t {
+    int r = 0;
+    uint32_t start = 0;
+    while (e >= start + pcnt[r]) {
+      start += pcnt[r];
+      ++r;
+    }
+    const int k = r < NODES ? r : r - NODES;
+    const Win& w = win[k];
+    const uint64_t idx = pbase[r] + (e - start);
+    uint32_t x, xs;
+    if (r < NODES) {
+      x = max(w.u0, w.P) + (e - start);
+      xs = a.tail_xsrc[idx];
+    } else {
+      x = a.pool_x[idx];
+      xs = a.pool_xsrc[idx];
+    }
+    meta = NONE;
+    if (xs == NONE || xs >= w.n1 + w.n2 || x < w.u0 || x >= w.u1) return 0;
+    const int d = 31 - __clz(k + 1);
+    meta = ((uint32_t)(LAM - 1 - d) << 16) | (w.off + (x - w.u0));
+    return w.s + xs;
+  };
+  uint32_t pm[PK];
+  R pv[PK];
+#pragma unroll
+  for (int i = 0; i < PK; ++i) {
+    pm[i] = NONE;
+    const uint32_t e = tid + 256 * i;
+    if (e < ptot) {
+      const uint64_t src = patch_at(e, pm[i]);
+      if (pm[i] != NONE) pv[i] = XR[src];
+    }
+  }
+
+  // 4. coin flips of every window of every level
+  const uint32_t nwords = win[NODES].wb;
+  for (uint32_t fb = tid; fb < nwords / 4; fb += 256) {
+    int k = 0;
+    while (k + 1 < NODES && 4 * fb >= win[k + 1].wb) ++k;
+    const Win& w = win[k];
+    const W4 f = flip_block(w.g0 + (fb - w.wb / 4), w.m, w.L, key);
+    *reinterpret_cast<uint4*>(&words[4 * fb]) = make_uint4(f.w[0], f.w[1], f.w[2], f.w[3]);
+  }
+  __syncthreads();
+  // zeros per word, scanned over all windows of all levels
+  {
+    uint32_t zl[KW];
+    uint32_t zs = 0;
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+      const uint32_t wi = tid * KW + k;
+      zl[k] = wi < nwords ? 32u - (uint32_t)__popc(words[wi]) : 0u;
+      zs += zl[k];
+    }
+    uint32_t run = block_excl_scan<256>(zs, tmp, nullptr);
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+      const uint32_t wi = tid * KW + k;
+      if (wi < NWORD) wpre[wi] = run;
+      run += zl[k];
+    }
+  }
+  // the staged runs land in LDS
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const uint32_t p = tid + 256 * i;
+    if (p < len) reinterpret_cast<R*>(buf[0])[p] = v[i];
+  }
+  __syncthreads();
+  // per window, what the interleave needs: slot t = s + toff for LDS slot s;
+  // before the break step, a zero flip takes A[z] (at off + z) and a one
+  // takes B[t - u0 - z] (at bdelta + t - z), z = zeros in [u0, t) = the
+  // wpre-based count minus zbase; from the break step on, t maps to t + pdelta
+  if (tid < NODES) {
+    const Win& w = win[tid];
+    const uint32_t la = w.ra1 - w.ra0;
+    const uint32_t wbase = w.wb - 4 * w.g0;
+    const uint32_t w0 = wbase + (w.u0 >> 5);
+    const uint32_t zbase =
+        w.u1 > w.u0 ? wpre[w0] + (uint32_t)__popc(~words[w0] & ((1u << (w.u0 & 31)) - 1u)) : 0u;
+    const uint32_t pdelta = w.side == 0 ? w.off + la - w.n1 - w.u0 + w.ra0 : w.off - w.n2 - w.ra0;
+    *reinterpret_cast<uint4*>(&hot[tid][0]) = make_uint4(w.u0 - w.off, w.P, wbase, zbase);
+    *reinterpret_cast<uint4*>(&hot[tid][4]) = make_uint4(w.off, w.off + la - w.u0, pdelta, 0u);
+  }
+  __syncthreads();
+
+  // 5. the levels, bottom up, each one interleave from one LDS buffer into
+  //    the other, then its insertion-loop slots
+#pragma unroll
+  for (int li = 0; li < LAM; ++li) {
+    const int d = LAM - 1 - li;
+    const int kf = (1 << d) - 1, kl = (2 << d) - 1;
+    const E* src = buf[li & 1];
+    E* dst = buf[(li + 1) & 1];
+    for (uint32_t base = 4 * tid; base < len; base += 1024) {
+      int k = kf;
+      while (k + 1 < kl && base >= win[k + 1].off) ++k;
+      uint32_t wend = k + 1 < kl ? win[k + 1].off : len;
+      uint4 h0 = *reinterpret_cast<const uint4*>(&hot[k][0]);
+      uint4 h1 = *reinterpret_cast<const uint4*>(&hot[k][4]);
+      uint32_t fr[4];
+      const uint32_t t0 = base + h0.x;
+      if (base + 4 <= wend && t0 + 4 <= h0.y && (t0 >> 5) == ((t0 + 3) >> 5)) {
+        // four slots of one window, one flip word, before the break step
+        const uint32_t wi = h0.z + (t0 >> 5);
+        const uint32_t word = words[wi] >> (t0 & 31);
+        uint32_t z = wpre[wi] - h0.w + (uint32_t)__popc(~words[wi] & ((1u << (t0 & 31)) - 1u));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t bit = (word >> j) & 1u;
+          fr[j] = bit ? h1.y + t0 + j - z : h1.x + z;
+          z += bit ^ 1u;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t s = min(base + j, len - 1);
+          while (s >= wend) {
+            ++k;
+            wend = k + 1 < kl ? win[k + 1].off : len;
+            h0 = *reinterpret_cast<const uint4*>(&hot[k][0]);
+            h1 = *reinterpret_cast<const uint4*>(&hot[k][4]);
+          }
+          const uint32_t t = s + h0.x;
+          if (t < h0.y) {
+            const uint32_t wi = h0.z + (t >> 5);
+            const uint32_t word = words[wi];
+            const uint32_t z = wpre[wi] - h0.w + (uint32_t)__popc(~word & ((1u << (t & 31)) - 1u));
+            fr[j] = ((word >> (t & 31)) & 1u) ? h1.y + t - z : h1.x + z;
+          } else {
+            fr[j] = t + h1.z;
+          }
+        }
+      }
+      if (sizeof(E) == 4 && base + 4 <= len) {
+        uint4 o;
+        o.x = *reinterpret_cast<const uint32_t*>(&src[fr[0]]);
+        o.y = *reinterpret_cast<const uint32_t*>(&src[fr[1]]);
+        o.z = *reinterpret_cast<const uint32_t*>(&src[fr[2]]);
+        o.w = *reinterpret_cast<const uint32_t*>(&src[fr[3]]);
+        *reinterpret_cast<uint4*>(&dst[base]) = o;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (base + j < len) dst[base + j] = src[fr[j]];
+      }
+    }
+    __syncthreads();
+    // insertion-loop slots of this level inside the tile
+#pragma unroll
+    for (int i = 0; i < PK; ++i)
+      if (pm[i] != NONE && (pm[i] >> 16) == (uint32_t)li && (pm[i] & 0xFFFFu) < (uint32_t)T)
+        reinterpret_cast<R*>(dst)[pm[i] & 0xFFFFu] = pv[i];
+    for (uint32_t e = 256 * PK + tid; e < ptot; e += 256) {
+      uint32_t meta;
+      const uint64_t srcx = patch_at(e, meta);
+      if (meta != NONE && (meta >> 16) == (uint32_t)li && (meta & 0xFFFFu) < (uint32_t)T)
+        dst[meta & 0xFFFFu] = X[srcx];
+    }
+    __syncthreads();
+  }
+
+  // 6. store the top window
+  const E* fin = buf[LAM & 1];
+  E* out = Z + sM + win[0].u0;
+  for (uint32_t o = 4 * tid; o < len; o += 1024) {
+    const uint32_t cnt = min(4u, len - o);
+    if (cnt == 4 && sizeof(E) == 4 && ((uintptr_t)(out + o) & 15) == 0) {
+      *reinterpret_cast<uint4*>(out + o) = *reinterpret_cast<const uint4*>(&fin[o]);
+    } else {
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k)
+        if (k < cnt) out[o + k] = fin[o + k];
+    }
+  }
+}
+
+// Slots per tile for 4-byte elements: 2048 (eight workgroups per CU, the
+// default: measured faster) or 4096 (MS_GROUP_TILE=4096).  A tuning knob only.
+static int group_tile_u32() {
+  static const int t = [] {
+    const char* e = getenv("MS_GROUP_TILE");
+    return e && atoi(e) == 4096 ? 4096 : 2048;
+  }();
+  return t;
+}
+
+int group_tile(uint32_t eb) { return eb == 4 ? group_tile_u32() : eb == 8 ? 2048 : 1024; }
+
+template <typename E, int T, int LAM>
+static void launch_group_l(const GroupArgs& a, uint64_t tiles, hipStream_t st) {
+  hipLaunchKernelGGL((group_kernel<E, T, LAM>), dim3((uint32_t)tiles), dim3(256), 0, st, a);
+}
+
+template <typename E, int T>
+static void launch_group_t(const GroupArgs& a, int lam, uint64_t tiles, hipStream_t st) {
+  if (lam == 1) launch_group_l<E, T, 1>(a, tiles, st);
+  else if (lam == 2) launch_group_l<E, T, 2>(a, tiles, st);
+  else launch_group_l<E, T, 3>(a, tiles, st);
+}
+
+void launch_group(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st) {
+  if (eb == 4) {
+    if (group_tile_u32() == 2048) launch_group_t<uint32_t, 2048>(a, lam, grid, st);
+    else launch_group_t<uint32_t, 4096>(a, lam, grid, st);
+  } else if (eb == 8) {
+    launch_group_t<uint64_t, 2048>(a, lam, grid, st);
+  } else {
+    launch_group_t<uint4, 1024>(a, lam, grid, st);
+  }
+}
+
+}  // namespace ms

@@ -22,6 +22,8 @@
 //         j_p >= P is itself a step before p, what j_p's own step fetched
 //         (followed recursively), or else C0[j_p];
 //     and is finally mapped to the input offset C0 reads it from.
+#include <algorithm>
+
 #include "ms_device.hpp"
 #include "ms_plan.hpp"
 
@@ -94,7 +96,7 @@ __device__ int select_in_block(const W4& f, uint32_t r, int want_one) {
 }
 
 // Slot of the (target+1)-th zero (want_one = 0) or one in chunk ch of merge m.
-__device__ uint32_t locate_in_chunk(const PlanArgs& pa, uint64_t chunk_global, uint32_t ch, uint32_t m,
+__device__ __forceinline__ uint32_t locate_in_chunk(const PlanArgs& pa, uint64_t chunk_global, uint32_t ch, uint32_t m,
                                     uint32_t L, uint32_t r, int want_one) {
   const uint16_t* zl = pa.zloc + (chunk_global << kChunkGranLog);
   // largest granule g with (zeros or ones before g) <= r
@@ -184,6 +186,7 @@ __device__ __forceinline__ uint32_t tail_draw(const PlanArgs& pa, uint32_t L, ui
 
 struct TailWg {
   const HbmLevel* lv;
+  int l;
   uint32_t m, w;
   MergeGeom g;
   uint32_t P, k;
@@ -193,6 +196,7 @@ struct TailWg {
 __device__ __forceinline__ TailWg tail_wg(const PlanArgs& pa, uint64_t wg) {
   TailWg t;
   const int l = level_of_wg(pa, wg);
+  t.l = l;
   t.lv = &pa.lev[l];
   const uint64_t rel = wg - t.lv->wg_base;
   t.m = (uint32_t)(rel / t.lv->wpm);
@@ -215,7 +219,7 @@ __global__ void __launch_bounds__(256) tail_count_kernel(PlanArgs pa) {
   for (uint32_t d = t.w * 256 + threadIdx.x; d < t.k; d += t.lv->wpm * 256) {
     const uint32_t i = t.P + d;
     const uint32_t j = tail_draw(pa, t.lv->L, t.m, i, &bits);
-    if (j != i) atomicAdd(&pa.bcnt[t.bb + (j >> kBucketLog)], 1u);
+    if (j != i) atomicAdd(&pa.bcnt[t.bb + (j >> t.lv->blog)], 1u);
   }
   const uint64_t s = block_sum_u64<256>(bits, red);
   if (threadIdx.x == 0 && s) atomicAdd(pa.bits, (unsigned long long)s);
@@ -298,7 +302,7 @@ __global__ void __launch_bounds__(256) tail_scatter_kernel(PlanArgs pa) {
     const uint32_t i = t.P + d;
     const uint32_t j = tail_draw(pa, t.lv->L, t.m, i, &bits);
     if (j == i) continue;
-    const uint64_t b = t.bb + (j >> kBucketLog);
+    const uint64_t b = t.bb + (j >> t.lv->blog);
     const uint64_t slot = (uint64_t)pa.boff[b] + atomicAdd(&pa.bfill[b], 1u);
     if (slot < pa.pool_cap) {
       pa.pool_x[slot] = j;
@@ -308,8 +312,9 @@ __global__ void __launch_bounds__(256) tail_scatter_kernel(PlanArgs pa) {
 }
 
 // Largest step s' < below among the steps that target slot y (y's own step excluded).
-__device__ __forceinline__ uint32_t max_target(const PlanArgs& pa, uint64_t bb, uint32_t y, uint32_t below) {
-  const uint64_t b = bb + (y >> kBucketLog);
+__device__ __forceinline__ uint32_t max_target(const PlanArgs& pa, uint64_t bb, uint32_t blog, uint32_t y,
+                                               uint32_t below) {
+  const uint64_t b = bb + (y >> blog);
   const uint64_t lo = pa.boff[b];
   uint64_t hi = lo + pa.bcnt[b];
   if (hi > pa.pool_cap) hi = pa.pool_cap;
@@ -350,14 +355,14 @@ __global__ void __launch_bounds__(256) tail_resolve_kernel(PlanArgs pa) {
   for (uint32_t d = t.w * 256 + threadIdx.x; d < t.k; d += lv.wpm * 256) {
     const uint32_t x = t.P + d;
     uint32_t out = kNone32;
-    if (max_target(pa, t.bb, x, kNone32) == kNone32) {
+    if (max_target(pa, t.bb, lv.blog, x, kNone32) == kNone32) {
       // no later step targets x: it keeps what its own step fetched from j_x
       uint32_t dummy = 0;
       uint32_t s = x;
       uint32_t y = tail_draw(pa, lv.L, t.m, x, &dummy);
       uint32_t src;
       for (;;) {
-        const uint32_t q = max_target(pa, t.bb, y, s);
+        const uint32_t q = max_target(pa, t.bb, lv.blog, y, s);
         if (q != kNone32) { src = q; break; }      // last earlier step writing y
         if (y >= t.P && y < s) {                   // y's own step wrote it
           s = y;
@@ -379,9 +384,125 @@ __global__ void __launch_bounds__(256) tail_resolve_kernel(PlanArgs pa) {
     const uint32_t x = pa.pool_x[e];
     const uint32_t st = pa.pool_step[e];
     uint32_t out = kNone32;
-    if (max_target(pa, t.bb, x, kNone32) == st) out = c0_offset(pa, lv, t.m, t.g, t.P, side, st);
+    if (max_target(pa, t.bb, lv.blog, x, kNone32) == st) out = c0_offset(pa, lv, t.m, t.g, t.P, side, st);
     pa.pool_src[e] = out;
   }
+}
+
+// ---------------------------------------------------------------------------
+// 7. trace every resolved source down to the input of its fused pass
+// ---------------------------------------------------------------------------
+// The source of slot pos's final value at level lev[l], merge m, as an offset
+// into the output of the level below (relative to the merge's first element).
+__device__ __forceinline__ uint32_t final_source(const PlanArgs& pa, int l, uint32_t m, uint32_t pos) {
+  const HbmLevel& lv = pa.lev[l];
+  const uint64_t gm = lv.merge_base + m;
+  const MergeGeom g = merge_geom(pa, lv.L, m);
+  const uint32_t P = pa.P[gm];
+  const uint64_t bb = lv.bucket_base + (uint64_t)m * lv.bpm;
+  const uint64_t b = bb + (pos >> lv.blog);
+  const uint64_t lo = pa.boff[b];
+  uint64_t hi = lo + pa.bcnt[b];
+  if (hi > pa.pool_cap) hi = pa.pool_cap;
+  for (uint64_t e = lo; e < hi; ++e)
+    if (pa.pool_x[e] == pos && pa.pool_src[e] != kNone32) return pa.pool_src[e];
+  if (pos >= P) {
+    const uint64_t t = (uint64_t)pa.toff[gm] + (pos - P);
+    if (t < pa.tail_cap && pa.tail_src[t] != kNone32) return pa.tail_src[t];
+  }
+  return c0_offset(pa, lv, m, g, P, pa.side[gm], pos);
+}
+
+__device__ __forceinline__ uint32_t trace_to_input(const PlanArgs& pa, int l, uint32_t m, uint32_t off) {
+  if (off == kNone32) return kNone32;
+  const uint64_t s0 = merge_geom(pa, pa.lev[l].L, m).s;
+  uint64_t abs = s0 + off;
+  while (!pa.lev[l].group_bottom) {
+    const MergeGeom g = merge_geom(pa, pa.lev[l].L, m);
+    const uint32_t child = abs < g.s + g.n1 ? 2 * m : 2 * m + 1;
+    l -= 1;
+    const uint64_t cs = merge_geom(pa, pa.lev[l].L, child).s;
+    abs = cs + final_source(pa, l, child, (uint32_t)(abs - cs));
+    m = child;
+  }
+  return (uint32_t)(abs - s0);
+}
+
+__global__ void __launch_bounds__(256) trace_kernel(PlanArgs pa) {
+  const TailWg t = tail_wg(pa, blockIdx.x);
+  const int l = t.l;
+  const uint64_t toff = pa.toff[t.gm];
+  for (uint32_t d = t.w * 256 + threadIdx.x; d < t.k; d += t.lv->wpm * 256) {
+    if (toff + d >= pa.tail_cap) break;
+    pa.tail_xsrc[toff + d] = trace_to_input(pa, l, t.m, pa.tail_src[toff + d]);
+  }
+  const uint64_t lo = pa.boff[t.bb];
+  uint64_t hi = pa.boff[t.bb + t.lv->bpm];
+  if (hi > pa.pool_cap) hi = pa.pool_cap;
+  for (uint64_t e = lo + (uint64_t)t.w * 256 + threadIdx.x; e < hi; e += (uint64_t)t.lv->wpm * 256)
+    pa.pool_xsrc[e] = trace_to_input(pa, l, t.m, pa.pool_src[e]);
+}
+
+// ---------------------------------------------------------------------------
+// 8. fused passes: boundary records of every tile
+// ---------------------------------------------------------------------------
+// Slots the coin-flip loop of merge m (level lev[l]) filled from A before slot u.
+__device__ __forceinline__ uint32_t rank_at(const PlanArgs& pa, int l, uint32_t m, uint32_t u) {
+  const HbmLevel& lv = pa.lev[l];
+  const uint64_t gm = lv.merge_base + m;
+  const uint32_t P = pa.P[gm];
+  if (u >= P) {
+    const MergeGeom g = merge_geom(pa, lv.L, m);
+    return pa.side[gm] == 0 ? g.n1 : u - g.n2;
+  }
+  const uint64_t cg = lv.chunk_base + (uint64_t)m * lv.cpm + (u >> kChunkLog);
+  uint32_t z = pa.zc[cg] + pa.zloc[(cg << kChunkGranLog) + ((u >> kGranLog) & 255)];
+  if (u & 127u) {
+    const W4 f = flip_block(u >> kGranLog, m, lv.L, Key{pa.key0, pa.key1});
+    const uint32_t wsel = (u >> 5) & 3;
+    for (uint32_t w = 0; w < wsel; ++w) z += 32u - (uint32_t)__popc(pick(f, w));
+    z += (uint32_t)__popc(~pick(f, wsel) & ((1u << (u & 31)) - 1u));
+  }
+  return z;
+}
+
+// One thread per boundary record: the window tree at slot b*T of top merge M
+// (node 0 = the top window's start; a node's children start at its rank in
+// the left half and at its slot minus its rank in the right half).
+__global__ void __launch_bounds__(256) bounds_kernel(PlanArgs pa) {
+  const uint64_t idx = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= pa.total_bnd) return;
+  int g = (int)pa.ngroup - 1;
+  while (g > 0 && pa.grp[g].bnd_first > idx) --g;
+  const GroupInfo& gi = pa.grp[g];
+  const uint64_t local = idx - gi.bnd_first;
+  const uint32_t M = (uint32_t)(local / (gi.tpm + 1));
+  const uint32_t b = (uint32_t)(local % (gi.tpm + 1));
+  const int lt = (int)(gi.lf + gi.lam - 1);
+  const MergeGeom gt = merge_geom(pa, pa.lev[lt].L, M);
+  const int nodes = (1 << gi.lam) - 1;
+  uint32_t u[7], ra[7];
+  u[0] = (uint32_t)min((uint64_t)b * gi.T, (uint64_t)gt.N);
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    if (k < nodes) {
+      const int d = 31 - __clz(k + 1);
+      const int l = lt - d;
+      const uint32_t m = (M << d) + (uint32_t)(k - ((1 << d) - 1));
+      ra[k] = rank_at(pa, l, m, u[k]);
+      if (2 * k + 2 < 7 && 2 * k + 2 < nodes) {
+        u[2 * k + 1] = ra[k];
+        u[2 * k + 2] = u[k] - ra[k];
+      }
+    }
+  }
+  uint32_t* rec = pa.bnd + idx * kBndStride;
+#pragma unroll
+  for (int k = 0; k < 7; ++k)
+    if (k < nodes) {
+      rec[2 * k] = u[k];
+      rec[2 * k + 1] = ra[k];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -396,6 +517,10 @@ void launch_plan(const PlanArgs& pa, hipStream_t st) {
   launch_scan(pa.bcnt, pa.total_buckets, pa.part, pa.boff, pa.pool_cap, pa.status, 1u, st);
   hipLaunchKernelGGL(tail_scatter_kernel, dim3((uint32_t)pa.total_tail_wgs), dim3(256), 0, st, pa);
   hipLaunchKernelGGL(tail_resolve_kernel, dim3((uint32_t)pa.total_tail_wgs), dim3(256), 0, st, pa);
+  if (pa.tail_xsrc) {
+    hipLaunchKernelGGL(trace_kernel, dim3((uint32_t)pa.total_tail_wgs), dim3(256), 0, st, pa);
+    hipLaunchKernelGGL(bounds_kernel, dim3((uint32_t)((pa.total_bnd + 255) / 256)), dim3(256), 0, st, pa);
+  }
 }
 
 }  // namespace ms

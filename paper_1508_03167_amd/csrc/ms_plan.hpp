@@ -18,10 +18,10 @@
 namespace ms {
 
 constexpr int kMaxLevels = 32;
+constexpr int kGroupMax = 3;           // merge levels fused into one HBM pass, at most
 constexpr uint32_t kGranLog = 7;       // 128 flips per granule (one Philox block)
 constexpr uint32_t kChunkGranLog = 8;  // 256 granules per chunk
 constexpr uint32_t kChunkLog = kGranLog + kChunkGranLog;  // 32768 flips per chunk
-constexpr uint32_t kBucketLog = 12;    // tail-entry buckets of 4096 positions
 
 // One merge level that runs as an HBM pass.
 struct HbmLevel {
@@ -32,12 +32,26 @@ struct HbmLevel {
   uint32_t bpm;           // tail buckets per merge
   uint32_t wpm;           // tail workgroups per merge
   uint32_t tpm;           // merge-pass tiles per merge
+  uint32_t group_bottom;  // 1 if this level reads the pass input (first level of its fused pass)
+  uint32_t blog;          // target-entry buckets of 2^blog slots (about 2.5 sqrt(N): ~1.6 entries each)
+  uint32_t grp;           // fused pass this level belongs to
+  uint32_t gli;           // its index within the pass, 0 = the level reading the pass input
   uint32_t pad;
   uint64_t chunk_base;    // first chunk of this level (ctot, zc); granules at chunk_base << 8
   uint64_t merge_base;    // first merge of this level in the per-merge arrays
   uint64_t bucket_base;   // first bucket of this level
-  uint64_t pool_cap;      // bound on the tail entries of this level (grid sizing)
   uint64_t wg_base;       // first workgroup of this level in the tail kernels
+};
+
+// One fused pass: levels lev[lf .. lf+lam).  Its top level's merges are cut
+// into tiles of T output slots; a tile's "boundary record" holds, for each
+// node of the tile's window tree (breadth first, 2^lam - 1 nodes), the
+// window's start slot and the rank (zeros before it) at that slot.
+constexpr int kBndStride = 2 * ((1 << kGroupMax) - 1);  // u32 per boundary record
+struct GroupInfo {
+  uint32_t lf, lam;
+  uint32_t tpm, T;        // tiles per top merge, slots per tile
+  uint64_t bnd_first;     // first boundary record (each top merge has tpm + 1)
 };
 
 struct PlanArgs {
@@ -69,9 +83,70 @@ struct PlanArgs {
   uint32_t* pool_x;       // target entry: merge-relative slot j
   uint32_t* pool_step;    // target entry: the step i that writes C0[i] into slot j
   uint32_t* pool_src;     // target entry: input offset of slot j's final value, or ~0
+  uint32_t* tail_xsrc;    // as tail_src, traced down to the input of the fused pass
+  uint32_t* pool_xsrc;    // as pool_src, traced down to the input of the fused pass
+  uint32_t* bnd;          // boundary records of every fused pass
+  uint64_t total_bnd;
   unsigned long long* bits;
   uint32_t* status;
+  uint32_t ngroup;
+  uint32_t pad1;
   HbmLevel lev[kMaxLevels];
+  GroupInfo grp[kMaxLevels];
+};
+
+
+// Arguments of the data kernels (shared by the host runtime and the kernels).
+struct LeafArgs {
+  const void* in;
+  void* out;
+  uint64_t n;
+  uint32_t c;
+  uint32_t lds_levels;
+  uint32_t key0, key1;
+  unsigned long long* bits;
+};
+
+struct PassArgs {
+  const void* in;
+  void* out;
+  uint64_t n;
+  uint32_t c, L, tpm, cpm;
+  uint64_t chunk_base;  // global chunk of merge 0 of this level
+  uint64_t merge_base;  // global merge index of merge 0 of this level
+  const uint16_t* zloc;
+  const uint32_t* zc;
+  const uint32_t* P;
+  const uint8_t* side;
+  uint32_t key0, key1;
+  uint32_t vec_ok;  // base pointer 16-byte aligned
+};
+
+struct GroupArgs {
+  const void* X;
+  void* Z;
+  uint64_t n;
+  uint32_t c;
+  uint32_t tpm;     // tiles per top merge
+  uint32_t key0, key1;
+  uint32_t vec_ok;  // input and output 16-byte aligned
+  uint32_t ntiles;  // tiles of this pass (top merges x tpm)
+  const uint32_t* P;
+  const uint8_t* side;
+  const uint32_t* toff;       // per merge: first insertion step in the dense arrays
+  const uint32_t* bnd;        // boundary records of this pass (first one of top merge 0)
+  const uint32_t* tail_xsrc;  // per insertion step: pass-input offset of the slot's final value, or ~0
+  const uint32_t* boff;       // per bucket (+1): first target entry
+  const uint32_t* pool_x;     // target entry: slot
+  const uint32_t* pool_xsrc;  // target entry: pass-input offset of the slot's final value, or ~0
+  uint64_t tail_cap, pool_cap;
+  // per level of the pass, bottom first
+  uint32_t L[kGroupMax];
+  uint32_t blog[kGroupMax];
+  uint32_t bpm[kGroupMax];
+  uint32_t pad2;
+  uint64_t merge_base[kGroupMax];
+  uint64_t bucket_base[kGroupMax];
 };
 
 }  // namespace ms

@@ -79,6 +79,18 @@ def test_result_independent_of_lds_levels(M, n):
         assert gbits == wbits, kw
 
 
+@pytest.mark.parametrize("n,B", [(65537, 4096), (300007, 4096), (1048576 + 12345, 4096), (3000017, 4096),
+                                 (200000, 100), (777777, 7), (1 << 21, 2048)])
+def test_result_independent_of_levels_per_pass(M, n, B):
+    _say(f"[gpu] levels-per-pass variants n={n} B={B}")
+    want, wbits = O.permutation(n, B, 11)
+    for kw in ({"levels_per_pass": 1}, {"levels_per_pass": 2}, {"levels_per_pass": 3},
+               {"levels_per_pass": 2, "hbm_only": True}, {"levels_per_pass": 3, "hbm_only": True}):
+        got, gbits = gpu_perm(M, n, 11, leaf_B=B, **kw)
+        assert np.array_equal(got, want), (kw, int(np.argmax(got != want)))
+        assert gbits == wbits, kw
+
+
 @pytest.mark.parametrize("n", [1000, 4097, 65537, 300007])
 def test_shuffle_u32_equals_permutation_of_identity(M, n):
     import torch

@@ -34,7 +34,8 @@ def test_plan_matches_the_driver_partition():
     assert (p["levels"], p["leaves"], p["leaf_B"]) == (8, 256, 4096)
     assert p["lds_levels"] + p["hbm_levels"] == 8
     p = M.plan(1 << 30)
-    assert p["levels"] == 18 and p["lds_levels"] == 3 and p["hbm_levels"] == 15
+    # a 64 KiB super-block holds four leaves of 4096 u32: two merge levels in LDS
+    assert p["levels"] == 18 and p["lds_levels"] == 2 and p["hbm_levels"] == 16
     assert p["scratch_bytes"] >= 4 << 30
     p = M.plan(1 << 27, 16)
     assert p["levels"] == 15
