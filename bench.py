@@ -26,6 +26,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -69,6 +71,115 @@ def cpu_baseline(n_log2: int):
                       f"OpenMP over the blocks and over the merges of a level"}
 
 
+def bench_batched(M, torch, reps: int = 3, count: int = 4096, seed: int = 3):
+    """4096 uint32 arrays of log-uniform sizes in [2^8, 2^20] (seed_a = 3 + a),
+    resident in HBM: one batched call against one call per array."""
+    from paper_1508_03167_amd import inputs
+
+    sizes = inputs.batched_sizes(count, seed)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    total = int(offs[-1])
+    buf = torch.arange(total, dtype=torch.int32, device="cuda:0")
+    views = [buf[int(offs[i]):int(offs[i + 1])] for i in range(count)]
+    M.shuffle_batched_(views, seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        M.shuffle_batched_(views, seed)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    for i, v in enumerate(views):
+        M.shuffle_(v, seed + i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for i, v in enumerate(views):
+            M.shuffle_(v, seed + i)
+    torch.cuda.synchronize()
+    tl = (time.perf_counter() - t0) / reps
+    small = int(sum(1 for v in sizes if M.plan(int(v))["hbm_levels"] == 0))
+    return {"workload": f"{count} uint32 arrays, sizes floor(2^(8+12u)), seed {seed}+a",
+            "arrays": count, "elements": total, "arrays_in_one_workgroup": small,
+            "batched_ms": round(tb * 1e3, 3), "batched_gelem_s": round(total / tb / 1e9, 3),
+            "loop_ms": round(tl * 1e3, 3), "loop_gelem_s": round(total / tl / 1e9, 3),
+            "speedup": round(tl / tb, 3)}
+
+
+def bench_served(M, torch, count: int = 400, seed: int = 5, load: float = 0.7):
+    """Requests of log-uniform size in [2^10, 2^26] elements, uint32 or uint64,
+    Poisson arrivals at `load` times the measured capacity; request r uses seed
+    5 + r.  Continuous batching (every arrived request goes into the next
+    batched call) against one call per request in arrival order."""
+    from paper_1508_03167_amd import inputs
+
+    reqs = inputs.served_requests(count, seed, rate_per_s=1.0)
+    nbytes = [r["n"] * r["elem_bytes"] for r in reqs]
+    offs = np.concatenate([[0], np.cumsum([(b + 255) // 256 * 256 for b in nbytes])])
+    pool = torch.randint(0, 255, (int(offs[-1]),), dtype=torch.uint8, device="cuda:0")
+    tens = []
+    for i, r in enumerate(reqs):
+        v = pool[int(offs[i]):int(offs[i]) + nbytes[i]]
+        tens.append(v.view(torch.int64 if r["elem_bytes"] == 8 else torch.int32))
+    total = sum(r["n"] for r in reqs)
+    # capacity: every request back to back in one batched call
+    M.shuffle_batched_(tens, seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    M.shuffle_batched_(tens, seed)
+    torch.cuda.synchronize()
+    cap = count / (time.perf_counter() - t0)
+    rate = load * cap
+    gaps = inputs.rng(seed + 1).exponential(1.0 / rate, size=count)
+    arrival = np.cumsum(gaps) - gaps[0]
+
+    def serve(batched: bool):
+        lat = np.zeros(count)
+        nxt = 0
+        start = time.perf_counter()
+        while nxt < count:
+            now = time.perf_counter() - start
+            if arrival[nxt] > now:
+                time.sleep(min(arrival[nxt] - now, 0.001))
+                continue
+            last = nxt + 1
+            if batched:
+                while last < count and arrival[last] <= now:
+                    last += 1
+                M.shuffle_batched_(tens[nxt:last], seed + nxt)
+            else:
+                M.shuffle_(tens[nxt], seed + nxt)
+            torch.cuda.synchronize()
+            done = time.perf_counter() - start
+            lat[nxt:last] = done - arrival[nxt:last]
+            nxt = last
+        return lat, time.perf_counter() - start
+
+    check = [0, count // 2, count - 1]
+    before = {i: tens[i].clone() for i in check}
+    torch.cuda.synchronize()
+    lat_b, span_b = serve(True)
+    # a request's result is the same alone as in a batch
+    same = True
+    for i in check:
+        y = before[i].clone()
+        M.shuffle_(y, seed + i)
+        torch.cuda.synchronize()
+        same = same and bool(torch.equal(tens[i], y))
+    lat_l, span_l = serve(False)
+
+    def q(a, p):
+        return round(float(np.percentile(a, p)) * 1e3, 3)
+
+    return {"workload": f"{count} requests, sizes floor(2^(10+16u)), uint32 or uint64, Poisson arrivals at "
+                        f"{load} x capacity, seed {seed}+r",
+            "requests": count, "elements": int(total), "capacity_req_s": round(cap, 1),
+            "arrival_rate_req_s": round(rate, 1),
+            "batched": {"p50_ms": q(lat_b, 50), "p99_ms": q(lat_b, 99), "gelem_s": round(total / span_b / 1e9, 3)},
+            "one_call_per_request": {"p50_ms": q(lat_l, 50), "p99_ms": q(lat_l, 99),
+                                     "gelem_s": round(total / span_l / 1e9, 3)},
+            "results_equal_alone_and_in_batch": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,7 +188,8 @@ def main():
     ap.add_argument("--n-log2", type=int, default=30)
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-log2", type=int, default=27)
+    ap.add_argument("--cpu-sample-log2", type=int, default=29)
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and served workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 2^28 uint32 (1 GiB) for counter calibration")
     args = ap.parse_args()
@@ -167,6 +279,12 @@ def main():
         "roofline_other": roofs["leaf" if dominant == "merge_pass" else "merge_pass"],
         "ms_per_step_by_kernel_class": breakdown,
     }
+    if not args.no_extra:
+        del x
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batched(M, torch)
+        torch.cuda.empty_cache()
+        out["served"] = bench_served(M, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_log2)
     print(json.dumps(out), flush=True)

@@ -26,6 +26,7 @@ void launch_group(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipSt
 int group_tile(uint32_t eb);
 void launch_plan(const PlanArgs& pa, hipStream_t st);
 void launch_leaf(const LeafArgs& a, uint32_t eb, bool ident, uint64_t grid, hipStream_t st);
+void launch_leaf_batch(const LeafBatch& jb, uint32_t njobs, uint32_t eb, hipStream_t st);
 void launch_merge_pass(const PassArgs& a, uint32_t eb, uint64_t grid, hipStream_t st);
 void launch_patch(const PlanArgs& pa, int l, const void* in, void* out, uint32_t eb, hipStream_t st);
 int leaf_capacity(uint32_t eb);
@@ -236,11 +237,19 @@ struct Arena {
   size_t plan_bytes = 0;
 };
 
+constexpr int kSideStreams = 4;
+
 struct DeviceCtx {
   bool init = false;
   uint32_t* status = nullptr;
   unsigned long long* dummy_bits = nullptr;
   std::map<hipStream_t, Arena> arenas;
+  // batched calls spread their large arrays over these streams (default
+  // priority), forked from and joined back into the caller's stream
+  bool side_init = false;
+  hipStream_t side[kSideStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kSideStreams] = {};
 };
 
 std::mutex g_mu;
@@ -467,20 +476,97 @@ int ms_shuffle_batched_ex(void* const* ptrs, const uint64_t* sizes, const uint32
   g_err.clear();
   if (count == 0) return MS_OK;
   if (!ptrs || !sizes) return fail(MS_ERR_INVALID, "null pointer or size array");
-  for (uint32_t a = 0; a < count; ++a) {
-    const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
-    HostPlan hp;
-    int rc = make_plan(sizes[a], eb, cfg, hp);
-    if (rc) return rc;
-    if (sizes[a] > 0 && !ptrs[a]) return fail(MS_ERR_INVALID, "array %u: null pointer", a);
+  const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::vector<uint32_t> large;
+  {
+    // every argument is checked before anything is launched
+    for (uint32_t a = 0; a < count; ++a) {
+      const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
+      HostPlan hp;
+      int rc = make_plan(sizes[a], eb, cfg, hp);
+      if (rc) return rc;
+      if (sizes[a] > 0 && !ptrs[a]) return fail(MS_ERR_INVALID, "array %u: null pointer", a);
+      if (((uintptr_t)ptrs[a]) % eb != 0) return fail(MS_ERR_INVALID, "array %u: pointer not aligned to %u bytes", a, eb);
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceCtx* dc;
+    int rc;
+    if ((rc = device_ctx(&dc))) return rc;
+    // arrays whose every merge level fits in one leaf workgroup: one
+    // workgroup each, kLeafBatch arrays per launch, per element size
+    LeafBatch jb[3];
+    uint32_t nj[3] = {0, 0, 0};
+    auto flush = [&](int cls) {
+      if (!nj[cls]) return;
+      ProfScope ps(1, st);
+      launch_leaf_batch(jb[cls], nj[cls], cls == 0 ? 4u : cls == 1 ? 8u : 16u, st);
+      nj[cls] = 0;
+    };
+    for (uint32_t a = 0; a < count; ++a) {
+      const uint64_t n = sizes[a];
+      if (n <= 1) continue;
+      const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
+      HostPlan hp;
+      make_plan(n, eb, cfg, hp);
+      if (hp.nlev) {
+        large.push_back(a);
+        continue;
+      }
+      const int cls = eb == 4 ? 0 : eb == 8 ? 1 : 2;
+      LeafArgs& la = jb[cls].job[nj[cls]++];
+      const uint64_t sa = seed + a;
+      la.in = ptrs[a];
+      la.out = ptrs[a];
+      la.n = n;
+      la.c = hp.c;
+      la.lds_levels = hp.lam;
+      la.key0 = (uint32_t)sa;
+      la.key1 = (uint32_t)(sa >> 32);
+      la.bits = d_bits_per_array ? d_bits_per_array + a : dc->dummy_bits;
+      if (nj[cls] == (uint32_t)kLeafBatch) flush(cls);
+    }
+    for (int cls = 0; cls < 3; ++cls) flush(cls);
+    HIP_TRY(hipGetLastError());
+    if (large.size() > 1 && !dc->side_init) {
+      for (int i = 0; i < kSideStreams; ++i) {
+        HIP_TRY(hipStreamCreateWithFlags(&dc->side[i], hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&dc->join[i], hipEventDisableTiming));
+      }
+      HIP_TRY(hipEventCreateWithFlags(&dc->fork, hipEventDisableTiming));
+      dc->side_init = true;
+    }
+    if (large.size() > 1) {
+      HIP_TRY(hipEventRecord(dc->fork, st));
+      for (int i = 0; i < kSideStreams; ++i) HIP_TRY(hipStreamWaitEvent(dc->side[i], dc->fork, 0));
+    }
   }
-  for (uint32_t a = 0; a < count; ++a) {
-    const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
-    int rc = run_one(ptrs[a], sizes[a], eb, seed + a, reinterpret_cast<hipStream_t>(stream), cfg,
-                     d_bits_per_array ? d_bits_per_array + a : nullptr, false);
-    if (rc) return rc;
+  // arrays that need HBM passes: the full path each, spread over the side
+  // streams so that their small launches overlap
+  if (large.empty()) return MS_OK;
+  DeviceCtx* dc;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int rc;
+    if ((rc = device_ctx(&dc))) return rc;
   }
-  return MS_OK;
+  int err = MS_OK;
+  for (size_t i = 0; i < large.size() && err == MS_OK; ++i) {
+    const uint32_t a = large[i];
+    const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
+    const hipStream_t s2 = large.size() > 1 ? dc->side[i % kSideStreams] : st;
+    err = run_one(ptrs[a], sizes[a], eb, seed + a, s2, cfg, d_bits_per_array ? d_bits_per_array + a : nullptr, false);
+  }
+  if (large.size() > 1) {
+    // joined even after an error, so that the caller's stream still orders
+    // after whatever was launched
+    const std::string msg = g_err;
+    for (int i = 0; i < kSideStreams; ++i) {
+      HIP_TRY(hipEventRecord(dc->join[i], dc->side[i]));
+      HIP_TRY(hipStreamWaitEvent(st, dc->join[i], 0));
+    }
+    g_err = msg;
+  }
+  return err;
 }
 
 int ms_shuffle_batched(void* const* ptrs, const uint64_t* sizes, uint32_t count, uint64_t seed, void* stream) {

@@ -165,6 +165,12 @@ __device__ __forceinline__ int select_one(uint32_t w, int r) {
   return __ffs(z) - 1;
 }
 
+// Register copy of an element: a native 4 x u32 vector for uint4, whose
+// wrapper type keeps an array of them out of registers.
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+template <typename E> struct RegOf { using type = E; };
+template <> struct RegOf<uint4> { using type = v4u; };
+
 // Leaf / merge bounds of the partition: block i is [n*i >> c, n*(i+1) >> c).
 __device__ __host__ __forceinline__ uint64_t bound(uint64_t n, uint64_t i, uint32_t c) {
   return (n * i) >> c;

@@ -325,9 +325,10 @@ __device__ __forceinline__ void lds_merge_tail(E* data, uint32_t* seen, uint32_t
   }
 }
 
+// One super-block sb of 2^lds_levels leaves: Fisher-Yates of each leaf, then
+// the merge levels among them, all in LDS.
 template <typename E, int SCAP, int NT, bool IDENT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 4 : 4)))
-leaf_kernel(LeafArgs a) {
+__device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) {
   constexpr int KW = (MergeAux<SCAP>::kWords + NT - 1) / NT;  // words per thread in scans
   constexpr int KS = (SCAP + NT - 1) / NT;                     // slots per thread
   constexpr int BPT = (SCAP / 4 + kLeafMaxMerges + NT - 1) / NT;  // step blocks per thread
@@ -343,7 +344,6 @@ leaf_kernel(LeafArgs a) {
   const int tid = threadIdx.x;
   const Key key{a.key0, a.key1};
   const uint32_t Lam = a.lds_levels;
-  const uint64_t sb = blockIdx.x;
   const uint64_t base = bound(a.n, sb << Lam, a.c);
   const uint32_t cnt = (uint32_t)(bound(a.n, (sb + 1) << Lam, a.c) - base);
   const E* in = reinterpret_cast<const E*>(a.in);
@@ -368,13 +368,15 @@ leaf_kernel(LeafArgs a) {
   for (uint32_t i = tid; i < cnt; i += NT) data[i] = IDENT ? ident_value<E>(base + i) : in[base + i];
   __syncthreads();
   {
-    E val[BPT][4];
+    using R = typename RegOf<E>::type;
+    R* dataR = reinterpret_cast<R*>(data);
+    R val[BPT][4];
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
       const uint32_t g = lt + tpl * k;
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (4 * g + e < b) val[k][e] = data[lb + get16(F[k][e >> 1], e & 1)];
+        if (4 * g + e < b) val[k][e] = dataR[lb + get16(F[k][e >> 1], e & 1)];
     }
     __syncthreads();
 #pragma unroll
@@ -382,7 +384,7 @@ leaf_kernel(LeafArgs a) {
       const uint32_t g = lt + tpl * k;
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (4 * g + e < b) data[lb + 4 * g + e] = val[k][e];
+        if (4 * g + e < b) dataR[lb + 4 * g + e] = val[k][e];
     }
     __syncthreads();
   }
@@ -478,18 +480,20 @@ leaf_kernel(LeafArgs a) {
       if (k & 1) SRC[k >> 1] |= src << 16;
       else SRC[k >> 1] = src;
     }
-    E val[KS];
+    using R = typename RegOf<E>::type;
+    R* dataR = reinterpret_cast<R*>(data);
+    R val[KS];
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
       const uint32_t s = tv + k * NT;
-      if (s < cnt) val[k] = data[get16(SRC[k >> 1], k & 1)];
+      if (s < cnt) val[k] = dataR[get16(SRC[k >> 1], k & 1)];
     }
     __syncthreads();
     asm volatile("" : "+v"(tv));
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
       const uint32_t s = tv + k * NT;
-      if (s < cnt) data[s] = val[k];
+      if (s < cnt) dataR[s] = val[k];
     }
     __syncthreads();
     // insertion loops, one wave per merge; the flip words are dead now and
@@ -688,6 +692,17 @@ __global__ void __launch_bounds__(256) patch_kernel(PlanArgs pa, int l, const vo
 // host launchers
 // ---------------------------------------------------------------------------
 template <typename E, int SCAP, int NT, bool IDENT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) leaf_kernel(LeafArgs a) {
+  leaf_body<E, SCAP, NT, IDENT>(a, blockIdx.x);
+}
+
+// Whole small arrays, one per workgroup.
+template <typename E, int SCAP, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) leaf_batch_kernel(LeafBatch jb) {
+  leaf_body<E, SCAP, NT, false>(jb.job[blockIdx.x], 0);
+}
+
+template <typename E, int SCAP, int NT, bool IDENT>
 static void launch_leaf_t(const LeafArgs& a, uint64_t grid, hipStream_t st) {
   hipLaunchKernelGGL((leaf_kernel<E, SCAP, NT, IDENT>), dim3((uint32_t)grid), dim3(NT), 0, st, a);
 }
@@ -709,6 +724,21 @@ int leaf_capacity(uint32_t eb) {
 }
 int leaf_max_block() { return 4097; }
 int leaf_max_levels() { return 6; }
+
+void launch_leaf_batch(const LeafBatch& jb, uint32_t njobs, uint32_t eb, hipStream_t st) {
+  const bool sm = leaf_small();
+  const dim3 g(njobs);
+  if (eb == 4) {
+    if (sm) hipLaunchKernelGGL((leaf_batch_kernel<uint32_t, 16384, 512>), g, dim3(512), 0, st, jb);
+    else hipLaunchKernelGGL((leaf_batch_kernel<uint32_t, 32768, 1024>), g, dim3(1024), 0, st, jb);
+  } else if (eb == 8) {
+    if (sm) hipLaunchKernelGGL((leaf_batch_kernel<uint64_t, 8192, 512>), g, dim3(512), 0, st, jb);
+    else hipLaunchKernelGGL((leaf_batch_kernel<uint64_t, 16384, 1024>), g, dim3(1024), 0, st, jb);
+  } else {
+    if (sm) hipLaunchKernelGGL((leaf_batch_kernel<uint4, 4096, 512>), g, dim3(512), 0, st, jb);
+    else hipLaunchKernelGGL((leaf_batch_kernel<uint4, 8192, 1024>), g, dim3(1024), 0, st, jb);
+  }
+}
 
 void launch_leaf(const LeafArgs& a, uint32_t eb, bool ident, uint64_t grid, hipStream_t st) {
   const bool sm = leaf_small();

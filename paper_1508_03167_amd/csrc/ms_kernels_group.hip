@@ -27,12 +27,6 @@ struct Win {
   uint64_t s;
 };
 
-// Register copy of an element: a native 4 x u32 vector for uint4, whose
-// wrapper type keeps an array of them out of registers.
-typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-template <typename E> struct RegOf { using type = E; };
-template <> struct RegOf<uint4> { using type = v4u; };
-
 template <typename E, int T, int LAM>
 __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
   constexpr int NODES = (1 << LAM) - 1;

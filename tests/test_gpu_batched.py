@@ -1,0 +1,103 @@
+"""GPU parity of the batched entry point: every array of a batch, whatever its
+size, element size or position in the batch, gets exactly the permutation the
+oracle gives for (its n, cutoff 4096, seed + its index), and the bits it used.
+
+Small arrays (every merge level inside one leaf workgroup) run together, up to
+64 per launch; larger ones take the full path on side streams.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    import paper_1508_03167_amd as M
+
+    M.lib()
+    return M
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _make(sizes, ebs, seed):
+    import torch
+
+    rng = np.random.default_rng(seed)
+    host, dev = [], []
+    for n, eb in zip(sizes, ebs):
+        if eb == 4:
+            v = np.arange(n, dtype=np.int32)
+            host.append(v)
+            dev.append(torch.from_numpy(v.copy()).cuda())
+        else:
+            v = rng.integers(0, 2**63, size=(n, eb // 8), dtype=np.int64)
+            host.append(v)
+            dev.append(torch.from_numpy(v.copy()).cuda())
+    return host, dev
+
+
+def _check(M, sizes, ebs, seed):
+    import torch
+
+    host, dev = _make(sizes, ebs, seed)
+    bits = torch.zeros(len(sizes), dtype=torch.int64, device="cuda")
+    M.shuffle_batched_(dev, seed, bits=bits)
+    torch.cuda.synchronize()
+    assert M.device_status() == 0
+    got_bits = bits.cpu().numpy()
+    for a, (n, eb) in enumerate(zip(sizes, ebs)):
+        want, wbits = O.permutation(n, 4096, seed + a)
+        got = dev[a].cpu().numpy()
+        if eb == 4:
+            assert np.array_equal(got.view(np.uint32), want), (a, n)
+        else:
+            assert np.array_equal(got, host[a][want.astype(np.int64)]), (a, n, eb)
+        assert got_bits[a] == wbits, (a, n)
+
+
+def test_mixed_sizes_and_element_sizes(M):
+    sizes = [0, 1, 2, 3, 100, 4096, 4097, 16384, 16385, 50000, 300007, 7, 8192, 65537]
+    ebs = [4, 4, 4, 8, 16, 4, 8, 4, 4, 16, 4, 8, 16, 4]
+    _say("[gpu] batched mixed")
+    _check(M, sizes, ebs, 21)
+
+
+def test_many_small_arrays_span_several_launches(M):
+    rng = np.random.default_rng(5)
+    sizes = [int(x) for x in rng.integers(2, 16385, size=150)]
+    _say("[gpu] batched 150 small")
+    _check(M, sizes, [4] * len(sizes), 1000)
+
+
+def test_log_uniform_sizes(M):
+    # sizes 2^(8 + 12u) as in the batched workload, capped for the oracle's sake
+    rng = np.random.default_rng(3)
+    sizes = [int(2 ** (8 + 9 * u)) for u in rng.random(120)]
+    _say("[gpu] batched log-uniform")
+    _check(M, sizes, [4] * len(sizes), 3)
+
+
+def test_batched_equals_one_call_per_array(M):
+    import torch
+
+    sizes = [5000, 20000, 3, 70000, 16384]
+    a = [torch.arange(n, dtype=torch.int32, device="cuda") for n in sizes]
+    b = [t.clone() for t in a]
+    M.shuffle_batched_(a, 77)
+    for i, t in enumerate(b):
+        M.shuffle_(t, 77 + i)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
