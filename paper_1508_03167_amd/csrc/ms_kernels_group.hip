@@ -23,7 +23,7 @@
 namespace ms {
 
 struct Win {
-  uint32_t m, L, u0, u1, ra0, ra1, off, P, side, n1, n2, g0, wb, toff;
+  uint32_t m, L, u0, u1, ra0, ra1, off, bo, P, side, n1, n2, g0, wb, toff;
   uint64_t s;
 };
 
@@ -38,15 +38,20 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
   constexpr int PK = 2;        // patches per thread fetched ahead of the levels
   constexpr uint32_t NONE = 0xFFFFFFFFu;
   using R = typename RegOf<E>::type;
-  __shared__ __align__(16) E buf[2][T];
+  // windows start at multiples of 4 slots (each input run's region is
+  // rounded up to 4), so every group of 4 slots lies in one window
+  constexpr int TB = T + 4 * (1 << LAM);
+  __shared__ __align__(16) E buf[2][TB];
   __shared__ __align__(16) uint32_t words[NWORD];
   __shared__ uint32_t wpre[NWORD];
   __shared__ uint32_t tmp[8];
   __shared__ __align__(16) uint32_t hot[NODES][8];
   __shared__ Win win[NODES + 1];
   __shared__ uint32_t rec[2][2 * NODES];  // boundary records at both tile edges
-  __shared__ uint32_t rs[2 * NB + 1];     // LDS start of each staged run (+ end)
-  __shared__ uint32_t rsrc[2 * NB];       // its first element, from the top merge's
+  __shared__ uint32_t rs[2 * NB + 1];     // first element of each staged run in run order (+ end)
+  __shared__ uint32_t rl[2 * NB];         // its LDS slot
+  __shared__ uint32_t rsrc[2 * NB];       // its first element in the pass input, from the top merge's
+  __shared__ uint32_t lgroups[LAM];       // groups of 4 slots per level
   // insertion-loop slots of the tile: per window, a range of the dense
   // per-step array (slots >= P) and a range of target entries (its buckets)
   __shared__ uint32_t pcnt[2 * NODES];
@@ -56,8 +61,16 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
   const E* X = reinterpret_cast<const E*>(a.X);
   const R* XR = reinterpret_cast<const R*>(a.X);
   E* Z = reinterpret_cast<E*>(a.Z);
-  const uint32_t tile = blockIdx.x;
-  if (tile >= a.ntiles) return;
+  if (blockIdx.x >= a.ntiles) return;
+  // Workgroups are dealt to the 8 XCDs round robin; give each XCD a
+  // contiguous eighth of the tiles so that the tiles of one merge share an
+  // L2, which then also serves most insertion-loop fetches within the merge.
+  uint32_t tile;
+  {
+    const uint32_t q = a.ntiles >> 3, r = a.ntiles & 7u;
+    const uint32_t x = blockIdx.x & 7u, i = blockIdx.x >> 3;
+    tile = x * q + min(x, r) + i;
+  }
   const uint32_t M = tile / a.tpm;
   const uint32_t b = tile - M * a.tpm;
 
@@ -80,6 +93,7 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
   if (rec[0][0] >= rec[1][0]) return;  // the top merge ends before this tile
 
   // 2. the window tree (one thread per window)
+  uint64_t bq_lo = 0, bq_hi = 0;  // the window's buckets of target entries (threads < NODES)
   if (tid < NODES) {
     const int k = tid;
     const int d = 31 - __clz(k + 1);
@@ -101,17 +115,31 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
     w.ra0 = rec[0][2 * k + 1];
     w.ra1 = rec[1][2 * k + 1];
     w.g0 = u0 >> kGranLog;
-    // LDS offset: a right child sits after its left sibling's window
+    // LDS layout: every window's region is the union of the regions of the
+    // 2^LAM input runs below it, each run rounded up to 4 slots; a window
+    // starts where its left child does and its right child after the left
+    // child's region
+    auto region = [&](int node) -> uint32_t {
+      const int dn = 31 - __clz(node + 1);
+      const int first = ((node + 1) << (LAM - 1 - dn)) - 1;
+      uint32_t S = 0;
+      for (int q = first; q < first + (1 << (LAM - 1 - dn)); ++q) {
+        const uint32_t la = rec[1][2 * q + 1] - rec[0][2 * q + 1], ln = rec[1][2 * q] - rec[0][2 * q];
+        S += ((la + 3u) & ~3u) + ((ln - la + 3u) & ~3u);
+      }
+      return S;
+    };
     uint32_t off = 0, node = 0;
     for (int j = d; j-- > 0;) {
       if ((idx >> j) & 1u) {
-        off += rec[1][2 * node + 1] - rec[0][2 * node + 1];
+        off += region(2 * node + 1);
         node = 2 * node + 2;
       } else {
         node = 2 * node + 1;
       }
     }
     w.off = off;
+    w.bo = d == LAM - 1 ? ((rec[1][2 * k + 1] - rec[0][2 * k + 1] + 3u) & ~3u) : region(2 * k + 1);
     // flip words: nodes in breadth-first order, whole granules per window
     uint32_t wb = 0;
     for (int j = 0; j < k; ++j) {
@@ -124,8 +152,14 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
       const uint32_t j = (uint32_t)(k - NODES / 2);
       const uint64_t sTop = bound(a.n, (uint64_t)M << a.L[LAM - 1], a.c);
       const uint32_t rel = (uint32_t)(s0 - sTop);
-      rs[2 * j] = off;
-      rs[2 * j + 1] = off + (w.ra1 - w.ra0);
+      // runs in tree order: their element counts add up to the tile's length
+      uint32_t before = 0;
+      for (int q = NODES / 2; q < k; ++q) before += rec[1][2 * q] - rec[0][2 * q];
+      const uint32_t la = w.ra1 - w.ra0;
+      rs[2 * j] = before;
+      rs[2 * j + 1] = before + la;
+      rl[2 * j] = off;
+      rl[2 * j + 1] = off + w.bo;
       rsrc[2 * j] = rel + w.ra0;
       rsrc[2 * j + 1] = rel + w.n1 + (u0 - w.ra0);
       if (k == NODES - 1) rs[2 * j + 2] = rec[1][0] - rec[0][0];
@@ -139,19 +173,13 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
     uint32_t sc = x1 - x0;
     if (sb >= a.tail_cap) sc = 0;
     else if (sb + sc > a.tail_cap) sc = (uint32_t)(a.tail_cap - sb);
-    uint64_t plo = 0;
-    uint32_t pc = 0;
     if (u1 > u0) {
       const uint64_t bb = a.bucket_base[li] + (uint64_t)w.m * a.bpm[li];
-      plo = a.boff[bb + (u0 >> a.blog[li])];
-      uint64_t phi = a.boff[bb + ((u1 - 1) >> a.blog[li]) + 1];
-      if (phi > a.pool_cap) phi = a.pool_cap;
-      pc = phi > plo ? (uint32_t)(phi - plo) : 0u;
+      bq_lo = bb + (u0 >> a.blog[li]);
+      bq_hi = bb + ((u1 - 1) >> a.blog[li]) + 1;
     }
     pcnt[k] = sc;
     pbase[k] = sb;
-    pcnt[NODES + k] = pc;
-    pbase[NODES + k] = plo;
   }
   __syncthreads();
   const uint32_t len = win[0].u1 - win[0].u0;
@@ -160,6 +188,7 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
   // 3. loads: the 2^LAM runs of the pass input, and the first PK * 256
   //    insertion-loop patches (they land after the flips are counted)
   R v[PT];
+  uint32_t sl[PT];  // LDS slot of each staged element (TB = none)
   {
     int r = 0;
     uint32_t si[PT];
@@ -167,21 +196,30 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
     for (int i = 0; i < PT; ++i) {
       const uint32_t p = tid + 256 * i;
       si[i] = 0;
+      sl[i] = TB;
       if (p < len) {
         while (p >= rs[r + 1]) ++r;
         si[i] = rsrc[r] + (p - rs[r]);
+        sl[i] = rl[r] + (p - rs[r]);
       }
     }
 #pragma unroll
     for (int i = 0; i < PT; ++i) v[i] = XR[sM + si[i]];
   }
-  uint32_t ptot = 0;
+  // the bucket offsets of the target entries are in flight with the runs
+  uint32_t boff_lo = 0, boff_hi = 0;
+  if (tid < NODES && bq_hi > bq_lo) {
+    boff_lo = a.boff[bq_lo];
+    boff_hi = a.boff[bq_hi];
+  }
+  uint32_t stot = 0;
 #pragma unroll
-  for (int r = 0; r < 2 * NODES; ++r) ptot += pcnt[r];
-  // patch e of the tile: its level (bits 16..), LDS slot (bits 0..15) and
-  // pass-input offset, or NONE
-  auto patch_at = [&](uint32_t e, uint32_t& meta) -> uint64_t {
-    int r = 0;
+  for (int r = 0; r < NODES; ++r) stot += pcnt[r];
+  // patch e of the ranges from rbeg on: its level (bits 16..), LDS slot
+  // (bits 0..15) and pass-input offset, or NONE.  Ranges 0..NODES-1 are the
+  // windows' insertion steps, NODES..2*NODES-1 their target entries.
+  auto patch_at = [&](int rbeg, uint32_t e, uint32_t& meta) -> uint64_t {
+    int r = rbeg;
     uint32_t start = 0;
     while (e >= start + pcnt[r]) {
       start += pcnt[r];
@@ -204,14 +242,14 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
     meta = ((uint32_t)(LAM - 1 - d) << 16) | (w.off + (x - w.u0));
     return w.s + xs;
   };
-  uint32_t pm[PK];
-  R pv[PK];
+  uint32_t pm[2 * PK];
+  R pv[2 * PK];
 #pragma unroll
   for (int i = 0; i < PK; ++i) {
     pm[i] = NONE;
     const uint32_t e = tid + 256 * i;
-    if (e < ptot) {
-      const uint64_t src = patch_at(e, pm[i]);
+    if (e < stot) {
+      const uint64_t src = patch_at(0, e, pm[i]);
       if (pm[i] != NONE) pv[i] = XR[src];
     }
   }
@@ -244,101 +282,113 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
       run += zl[k];
     }
   }
-  // the staged runs land in LDS
+  // the staged runs land in LDS; the target-entry ranges are known now
 #pragma unroll
-  for (int i = 0; i < PT; ++i) {
-    const uint32_t p = tid + 256 * i;
-    if (p < len) reinterpret_cast<R*>(buf[0])[p] = v[i];
+  for (int i = 0; i < PT; ++i)
+    if (sl[i] < (uint32_t)TB) reinterpret_cast<R*>(buf[0])[sl[i]] = v[i];
+  if (tid < NODES) {
+    const uint64_t hi = min((uint64_t)boff_hi, a.pool_cap);
+    pcnt[NODES + tid] = hi > boff_lo ? (uint32_t)(hi - boff_lo) : 0u;
+    pbase[NODES + tid] = boff_lo;
   }
   __syncthreads();
+  uint32_t ptot = 0;
+#pragma unroll
+  for (int r = NODES; r < 2 * NODES; ++r) ptot += pcnt[r];
+#pragma unroll
+  for (int i = 0; i < PK; ++i) {
+    pm[PK + i] = NONE;
+    const uint32_t e = tid + 256 * i;
+    if (e < ptot) {
+      const uint64_t src = patch_at(NODES, e, pm[PK + i]);
+      if (pm[PK + i] != NONE) pv[PK + i] = XR[src];
+    }
+  }
   // per window, what the interleave needs: slot t = s + toff for LDS slot s;
   // before the break step, a zero flip takes A[z] (at off + z) and a one
   // takes B[t - u0 - z] (at bdelta + t - z), z = zeros in [u0, t) = the
-  // wpre-based count minus zbase; from the break step on, t maps to t + pdelta
+  // wpre-based count minus zbase; from the break step on, t maps to t + pdelta.
+  // gpre: groups of 4 slots in the windows before it on its level.
   if (tid < NODES) {
     const Win& w = win[tid];
-    const uint32_t la = w.ra1 - w.ra0;
+    const int d = 31 - __clz(tid + 1);
+    const uint32_t la4 = w.bo;  // the B input starts la4 slots after the window
     const uint32_t wbase = w.wb - 4 * w.g0;
     const uint32_t w0 = wbase + (w.u0 >> 5);
     const uint32_t zbase =
         w.u1 > w.u0 ? wpre[w0] + (uint32_t)__popc(~words[w0] & ((1u << (w.u0 & 31)) - 1u)) : 0u;
-    const uint32_t pdelta = w.side == 0 ? w.off + la - w.n1 - w.u0 + w.ra0 : w.off - w.n2 - w.ra0;
+    const uint32_t pdelta = w.side == 0 ? w.off + la4 - w.n1 - w.u0 + w.ra0 : w.off - w.n2 - w.ra0;
+    uint32_t gpre = 0;
+    for (int q = (1 << d) - 1; q < tid; ++q) gpre += (win[q].u1 - win[q].u0 + 3u) >> 2;
     *reinterpret_cast<uint4*>(&hot[tid][0]) = make_uint4(w.u0 - w.off, w.P, wbase, zbase);
-    *reinterpret_cast<uint4*>(&hot[tid][4]) = make_uint4(w.off, w.off + la - w.u0, pdelta, 0u);
+    *reinterpret_cast<uint4*>(&hot[tid][4]) = make_uint4(w.off, w.off + la4 - w.u0, pdelta, gpre);
+    if (tid == (2 << d) - 2) lgroups[LAM - 1 - d] = gpre + ((w.u1 - w.u0 + 3u) >> 2);
   }
   __syncthreads();
 
   // 5. the levels, bottom up, each one interleave from one LDS buffer into
-  //    the other, then its insertion-loop slots
+  //    the other (4 slots of one window per thread and step), then its
+  //    insertion-loop slots
 #pragma unroll
   for (int li = 0; li < LAM; ++li) {
     const int d = LAM - 1 - li;
     const int kf = (1 << d) - 1, kl = (2 << d) - 1;
     const E* src = buf[li & 1];
     E* dst = buf[(li + 1) & 1];
-    for (uint32_t base = 4 * tid; base < len; base += 1024) {
+    const uint32_t ng = lgroups[li];
+    for (uint32_t g = tid; g < ng; g += 256) {
       int k = kf;
-      while (k + 1 < kl && base >= win[k + 1].off) ++k;
-      uint32_t wend = k + 1 < kl ? win[k + 1].off : len;
-      uint4 h0 = *reinterpret_cast<const uint4*>(&hot[k][0]);
-      uint4 h1 = *reinterpret_cast<const uint4*>(&hot[k][4]);
+      while (k + 1 < kl && g >= hot[k + 1][7]) ++k;
+      const uint4 h0 = *reinterpret_cast<const uint4*>(&hot[k][0]);
+      const uint4 h1 = *reinterpret_cast<const uint4*>(&hot[k][4]);
+      const uint32_t s0 = h1.x + 4 * (g - h1.w);
+      const uint32_t t0 = s0 + h0.x;
+      const uint32_t wi = min(h0.z + (t0 >> 5), (uint32_t)NWORD - 2);
+      const uint32_t wlo = words[wi], whi = words[wi + 1];
+      uint32_t z = wpre[wi] - h0.w + (uint32_t)__popc(~wlo & ((1u << (t0 & 31)) - 1u));
+      const uint32_t bits4 = (uint32_t)((((uint64_t)whi << 32) | wlo) >> (t0 & 31));
       uint32_t fr[4];
-      const uint32_t t0 = base + h0.x;
-      if (base + 4 <= wend && t0 + 4 <= h0.y && (t0 >> 5) == ((t0 + 3) >> 5)) {
-        // four slots of one window, one flip word, before the break step
-        const uint32_t wi = h0.z + (t0 >> 5);
-        const uint32_t word = words[wi] >> (t0 & 31);
-        uint32_t z = wpre[wi] - h0.w + (uint32_t)__popc(~words[wi] & ((1u << (t0 & 31)) - 1u));
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const uint32_t bit = (word >> j) & 1u;
-          fr[j] = bit ? h1.y + t0 + j - z : h1.x + z;
-          z += bit ^ 1u;
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const uint32_t s = min(base + j, len - 1);
-          while (s >= wend) {
-            ++k;
-            wend = k + 1 < kl ? win[k + 1].off : len;
-            h0 = *reinterpret_cast<const uint4*>(&hot[k][0]);
-            h1 = *reinterpret_cast<const uint4*>(&hot[k][4]);
-          }
-          const uint32_t t = s + h0.x;
-          if (t < h0.y) {
-            const uint32_t wi = h0.z + (t >> 5);
-            const uint32_t word = words[wi];
-            const uint32_t z = wpre[wi] - h0.w + (uint32_t)__popc(~word & ((1u << (t & 31)) - 1u));
-            fr[j] = ((word >> (t & 31)) & 1u) ? h1.y + t - z : h1.x + z;
-          } else {
-            fr[j] = t + h1.z;
-          }
-        }
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t t = t0 + j;
+        const uint32_t bit = (bits4 >> j) & 1u;
+        const uint32_t rk = bit ? h1.y + t - z : h1.x + z;
+        fr[j] = min(t < h0.y ? rk : t + h1.z, (uint32_t)TB - 1);
+        z += bit ^ 1u;
       }
-      if (sizeof(E) == 4 && base + 4 <= len) {
+      if constexpr (sizeof(E) == 4) {
         uint4 o;
         o.x = *reinterpret_cast<const uint32_t*>(&src[fr[0]]);
         o.y = *reinterpret_cast<const uint32_t*>(&src[fr[1]]);
         o.z = *reinterpret_cast<const uint32_t*>(&src[fr[2]]);
         o.w = *reinterpret_cast<const uint32_t*>(&src[fr[3]]);
-        *reinterpret_cast<uint4*>(&dst[base]) = o;
+        *reinterpret_cast<uint4*>(&dst[s0]) = o;
       } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (base + j < len) dst[base + j] = src[fr[j]];
+        const R* srcR = reinterpret_cast<const R*>(src);
+        R* dstR = reinterpret_cast<R*>(dst);
+        const R a0 = srcR[fr[0]], a1 = srcR[fr[1]], a2 = srcR[fr[2]], a3 = srcR[fr[3]];
+        dstR[s0] = a0;
+        dstR[s0 + 1] = a1;
+        dstR[s0 + 2] = a2;
+        dstR[s0 + 3] = a3;
       }
     }
     __syncthreads();
     // insertion-loop slots of this level inside the tile
 #pragma unroll
-    for (int i = 0; i < PK; ++i)
-      if (pm[i] != NONE && (pm[i] >> 16) == (uint32_t)li && (pm[i] & 0xFFFFu) < (uint32_t)T)
+    for (int i = 0; i < 2 * PK; ++i)
+      if (pm[i] != NONE && (pm[i] >> 16) == (uint32_t)li && (pm[i] & 0xFFFFu) < (uint32_t)TB)
         reinterpret_cast<R*>(dst)[pm[i] & 0xFFFFu] = pv[i];
+    for (uint32_t e = 256 * PK + tid; e < stot; e += 256) {
+      uint32_t meta;
+      const uint64_t srcx = patch_at(0, e, meta);
+      if (meta != NONE && (meta >> 16) == (uint32_t)li && (meta & 0xFFFFu) < (uint32_t)TB)
+        dst[meta & 0xFFFFu] = X[srcx];
+    }
     for (uint32_t e = 256 * PK + tid; e < ptot; e += 256) {
       uint32_t meta;
-      const uint64_t srcx = patch_at(e, meta);
-      if (meta != NONE && (meta >> 16) == (uint32_t)li && (meta & 0xFFFFu) < (uint32_t)T)
+      const uint64_t srcx = patch_at(NODES, e, meta);
+      if (meta != NONE && (meta >> 16) == (uint32_t)li && (meta & 0xFFFFu) < (uint32_t)TB)
         dst[meta & 0xFFFFu] = X[srcx];
     }
     __syncthreads();
