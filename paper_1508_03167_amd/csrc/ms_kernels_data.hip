@@ -73,32 +73,108 @@ __device__ __forceinline__ uint32_t get16(uint32_t packed, int half) { return (p
 // 16-bit list link.  Each thread owns blocks of 4 consecutive steps of one
 // leaf (the steps whose draws share one Philox block) and returns, packed two
 // per register, the leaf-relative source F of each of its slots.
-template <int BPT>
+template <int BPT, int NT>
 __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, uint32_t lb, uint32_t b, uint32_t u,
-                                                uint32_t lt, uint32_t tpl, Key key, uint32_t* bits,
+                                                uint32_t lt, uint32_t tpl, uint32_t cnt, Key key, uint32_t* bits,
                                                 uint32_t (&F)[BPT][2]) {
   constexpr uint32_t NONE = 0xFFFFu;
   uint32_t J[BPT][2];
-  // 1. draws j_r for r = b-1..1 and the list of steps per target slot
+  // 1. the draws j_r, r = 1..b-1, of this thread's blocks (r = 4g..4g+3,
+  //    g = lt + tpl*k).  The primary words go to the data region first (one
+  //    word per slot); then each lane runs the Fast Dice Roller of its draws
+  //    one after the other, so that a wave waits for the lane with the most
+  //    rounds in total rather than for the slowest lane of every draw.  The
+  //    result replaces the word.
+  uint32_t* W = reinterpret_cast<uint32_t*>(head);
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
     const uint32_t g = lt + tpl * k;
-    J[k][0] = J[k][1] = 0xFFFFFFFFu;
     if (4 * g < b) {
       const W4 db = draw_block(g, u, 0, key);
-      uint32_t jj[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint32_t r = 4 * g + e;
-        jj[e] = NONE;
-        if (r >= 1 && r < b) {
-          const Draw dr = fdr_draw((uint64_t)r + 1, db.w[e], 0, u, r, key);
-          *bits += dr.bits;
-          jj[e] = dr.v;
+      for (int e = 0; e < 4; ++e)
+        if (4 * g + e < b) W[lb + 4 * g + e] = db.w[e];
+    }
+  }
+  {
+    constexpr uint32_t QN = 4 * BPT;
+    uint32_t qi = 0;
+    uint32_t r = 4 * lt, w = 0, v = 1, c = 0, used = 0, left = 32, kk = r + 1, bk = 0;
+    bool valid = r >= 1 && r < b;
+    if (valid) {
+      w = W[lb + r];
+      bk = 32 - __clz(r);
+    }
+#pragma unroll 1
+    for (;;) {
+      bool done = true;
+      uint32_t res = 0;
+      if (valid) {
+        int jump = (int)bk - (32 - __clz(v));
+        if ((v << jump) <= kk - 1) jump += 1;
+        if (jump > (int)left) {
+          const Draw d = fdr_draw_slow((uint64_t)kk, w, 0, u, r, key);
+          res = d.v;
+          used = d.bits;
+        } else {
+          const uint32_t x = (w >> (left - jump)) & ((1u << jump) - 1u);
+          left -= jump;
+          used += (uint32_t)jump;
+          v <<= jump;
+          c = (c << jump) | x;
+          if (c < kk) {
+            res = c;
+          } else {
+            v -= kk;
+            c -= kk;
+            done = false;
+          }
         }
       }
-      // push r onto the list of slot j_r: the four swaps of a block go out
-      // together and only the rare lost races retry
+      if (done) {
+        if (valid) {
+          W[lb + r] = res;
+          *bits += used;
+        }
+        if (++qi == QN) break;
+        r = 4 * (lt + tpl * (qi >> 2)) + (qi & 3u);
+        valid = r >= 1 && r < b;
+        kk = r + 1;
+        v = 1;
+        c = 0;
+        used = 0;
+        left = 32;
+        if (valid) {
+          w = W[lb + r];
+          bk = 32 - __clz(r);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const uint32_t g = lt + tpl * k;
+    uint32_t jj[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t r = 4 * g + e;
+      jj[e] = (r >= 1 && r < b) ? W[lb + r] : NONE;
+    }
+    J[k][0] = jj[0] | (jj[1] << 16);
+    J[k][1] = jj[2] | (jj[3] << 16);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < (cnt + 1) / 2; i += NT) reinterpret_cast<uint32_t*>(head)[i] = 0xFFFFFFFFu;
+  __syncthreads();
+  // push r onto the list of slot j_r: the four steps of a block go out
+  // together and only the rare lost races retry
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const uint32_t g = lt + tpl * k;
+    if (4 * g < b) {
+      uint32_t jj[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) jj[e] = get16(J[k][e >> 1], e & 1);
       uint32_t cur[4];
       bool todo[4];
 #pragma unroll
@@ -127,8 +203,6 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
         }
         if (!any) break;
       }
-      J[k][0] = jj[0] | (jj[1] << 16);
-      J[k][1] = jj[2] | (jj[3] << 16);
     }
   }
   __syncthreads();
@@ -175,13 +249,16 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
     }
   }
   __syncthreads();
-  // 3. head[] now holds up(x)
+  // 3. head[] now holds up(x) and link[] nxt(r)
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
     const uint32_t g = lt + tpl * k;
 #pragma unroll
     for (int e = 0; e < 4; ++e)
-      if (4 * g + e < b) head[lb + 4 * g + e] = (uint16_t)get16(U[k][e >> 1], e & 1);
+      if (4 * g + e < b) {
+        head[lb + 4 * g + e] = (uint16_t)get16(U[k][e >> 1], e & 1);
+        link[lb + 4 * g + e] = (uint16_t)get16(X[k][e >> 1], e & 1);
+      }
   }
   __syncthreads();
   // 4. top() of every slot by pointer jumping over the up() links (each
@@ -233,7 +310,7 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const uint32_t x = 4 * g + e;
-        const uint32_t nx = get16(X[k][e >> 1], e & 1);
+        const uint32_t nx = x < b ? (uint32_t)link[lb + x] : NONE;
         const uint32_t t = x == 0 ? 0u : nx;
         f[e] = get16(J[k][e >> 1], e & 1);
         if (x < b && (x == 0 || nx != NONE)) {
@@ -359,10 +436,8 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
   const uint32_t b = (uint32_t)(bound(a.n, u + 1, a.c) - bound(a.n, u, a.c));
   uint16_t* head = reinterpret_cast<uint16_t*>(data);
   uint16_t* link = head + SCAP;
-  for (uint32_t i = tid; i < (cnt + 1) / 2; i += NT) reinterpret_cast<uint32_t*>(head)[i] = 0xFFFFFFFFu;
-  __syncthreads();
   uint32_t F[BPT][2];
-  leaf_fy_sources<BPT>(head, link, lb, b, (uint32_t)u, lt, tpl, key, &bits, F);
+  leaf_fy_sources<BPT, NT>(head, link, lb, b, (uint32_t)u, lt, tpl, cnt, key, &bits, F);
   (void)nleaf;
 
   for (uint32_t i = tid; i < cnt; i += NT) data[i] = IDENT ? ident_value<E>(base + i) : in[base + i];

@@ -27,14 +27,14 @@ struct Win {
   uint64_t s;
 };
 
-template <typename E, int T, int LAM>
-__global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
+template <typename E, int T, int LAM, int NT>
+__global__ void __launch_bounds__(NT) group_kernel(GroupArgs a) {
   constexpr int NODES = (1 << LAM) - 1;
   constexpr int NB = NODES / 2 + 1;  // bottom windows
   // flip words of every window: at most T/32 + 8 per window and level
   constexpr int NWORD = LAM * (T / 32) + 8 * NODES + 8 * LAM;
-  constexpr int KW = (NWORD + 255) / 256;
-  constexpr int PT = T / 256;  // staged elements per thread
+  constexpr int KW = (NWORD + NT - 1) / NT;
+  constexpr int PT = T / NT;  // staged elements per thread
   constexpr int PK = 2;        // patches per thread fetched ahead of the levels
   constexpr uint32_t NONE = 0xFFFFFFFFu;
   using R = typename RegOf<E>::type;
@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
   __shared__ __align__(16) E buf[2][TB];
   __shared__ __align__(16) uint32_t words[NWORD];
   __shared__ uint32_t wpre[NWORD];
-  __shared__ uint32_t tmp[8];
+  __shared__ uint32_t tmp[NT / 64 + 1];
   __shared__ __align__(16) uint32_t hot[NODES][8];
   __shared__ Win win[NODES + 1];
   __shared__ uint32_t rec[2][2 * NODES];  // boundary records at both tile edges
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
   const uint32_t len = win[0].u1 - win[0].u0;
   const uint64_t sM = win[0].s;
 
-  // 3. loads: the 2^LAM runs of the pass input, and the first PK * 256
+  // 3. loads: the 2^LAM runs of the pass input, and the first PK * NT
   //    insertion-loop patches (they land after the flips are counted)
   R v[PT];
   uint32_t sl[PT];  // LDS slot of each staged element (TB = none)
@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
     uint32_t si[PT];
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
-      const uint32_t p = tid + 256 * i;
+      const uint32_t p = tid + NT * i;
       si[i] = 0;
       sl[i] = TB;
       if (p < len) {
@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
 #pragma unroll
   for (int i = 0; i < PK; ++i) {
     pm[i] = NONE;
-    const uint32_t e = tid + 256 * i;
+    const uint32_t e = tid + NT * i;
     if (e < stot) {
       const uint64_t src = patch_at(0, e, pm[i]);
       if (pm[i] != NONE) pv[i] = XR[src];
@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
 
   // 4. coin flips of every window of every level
   const uint32_t nwords = win[NODES].wb;
-  for (uint32_t fb = tid; fb < nwords / 4; fb += 256) {
+  for (uint32_t fb = tid; fb < nwords / 4; fb += NT) {
     int k = 0;
     while (k + 1 < NODES && 4 * fb >= win[k + 1].wb) ++k;
     const Win& w = win[k];
@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
       zl[k] = wi < nwords ? 32u - (uint32_t)__popc(words[wi]) : 0u;
       zs += zl[k];
     }
-    uint32_t run = block_excl_scan<256>(zs, tmp, nullptr);
+    uint32_t run = block_excl_scan<NT>(zs, tmp, nullptr);
 #pragma unroll
     for (int k = 0; k < KW; ++k) {
       const uint32_t wi = tid * KW + k;
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
 #pragma unroll
   for (int i = 0; i < PK; ++i) {
     pm[PK + i] = NONE;
-    const uint32_t e = tid + 256 * i;
+    const uint32_t e = tid + NT * i;
     if (e < ptot) {
       const uint64_t src = patch_at(NODES, e, pm[PK + i]);
       if (pm[PK + i] != NONE) pv[PK + i] = XR[src];
@@ -336,7 +336,7 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
     const E* src = buf[li & 1];
     E* dst = buf[(li + 1) & 1];
     const uint32_t ng = lgroups[li];
-    for (uint32_t g = tid; g < ng; g += 256) {
+    for (uint32_t g = tid; g < ng; g += NT) {
       int k = kf;
       while (k + 1 < kl && g >= hot[k + 1][7]) ++k;
       const uint4 h0 = *reinterpret_cast<const uint4*>(&hot[k][0]);
@@ -379,13 +379,13 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
     for (int i = 0; i < 2 * PK; ++i)
       if (pm[i] != NONE && (pm[i] >> 16) == (uint32_t)li && (pm[i] & 0xFFFFu) < (uint32_t)TB)
         reinterpret_cast<R*>(dst)[pm[i] & 0xFFFFu] = pv[i];
-    for (uint32_t e = 256 * PK + tid; e < stot; e += 256) {
+    for (uint32_t e = NT * PK + tid; e < stot; e += NT) {
       uint32_t meta;
       const uint64_t srcx = patch_at(0, e, meta);
       if (meta != NONE && (meta >> 16) == (uint32_t)li && (meta & 0xFFFFu) < (uint32_t)TB)
         dst[meta & 0xFFFFu] = X[srcx];
     }
-    for (uint32_t e = 256 * PK + tid; e < ptot; e += 256) {
+    for (uint32_t e = NT * PK + tid; e < ptot; e += NT) {
       uint32_t meta;
       const uint64_t srcx = patch_at(NODES, e, meta);
       if (meta != NONE && (meta >> 16) == (uint32_t)li && (meta & 0xFFFFu) < (uint32_t)TB)
@@ -397,7 +397,7 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
   // 6. store the top window
   const E* fin = buf[LAM & 1];
   E* out = Z + sM + win[0].u0;
-  for (uint32_t o = 4 * tid; o < len; o += 1024) {
+  for (uint32_t o = 4 * tid; o < len; o += 4 * NT) {
     const uint32_t cnt = min(4u, len - o);
     if (cnt == 4 && sizeof(E) == 4 && ((uintptr_t)(out + o) & 15) == 0) {
       *reinterpret_cast<uint4*>(out + o) = *reinterpret_cast<const uint4*>(&fin[o]);
@@ -409,8 +409,9 @@ __global__ void __launch_bounds__(256) group_kernel(GroupArgs a) {
   }
 }
 
-// Slots per tile for 4-byte elements: 2048 (eight workgroups per CU, the
-// default: measured faster) or 4096 (MS_GROUP_TILE=4096).  A tuning knob only.
+// Slots per tile for 4-byte elements: 2048 with 256 threads (the default:
+// measured faster) or 4096 with 512 threads (MS_GROUP_TILE=4096).  A tuning
+// knob only: the permutation does not depend on it.
 static int group_tile_u32() {
   static const int t = [] {
     const char* e = getenv("MS_GROUP_TILE");
@@ -421,26 +422,22 @@ static int group_tile_u32() {
 
 int group_tile(uint32_t eb) { return eb == 4 ? group_tile_u32() : eb == 8 ? 2048 : 1024; }
 
-template <typename E, int T, int LAM>
-static void launch_group_l(const GroupArgs& a, uint64_t tiles, hipStream_t st) {
-  hipLaunchKernelGGL((group_kernel<E, T, LAM>), dim3((uint32_t)tiles), dim3(256), 0, st, a);
-}
-
-template <typename E, int T>
+template <typename E, int T, int NT>
 static void launch_group_t(const GroupArgs& a, int lam, uint64_t tiles, hipStream_t st) {
-  if (lam == 1) launch_group_l<E, T, 1>(a, tiles, st);
-  else if (lam == 2) launch_group_l<E, T, 2>(a, tiles, st);
-  else launch_group_l<E, T, 3>(a, tiles, st);
+  const dim3 g((uint32_t)tiles), b(NT);
+  if (lam == 1) hipLaunchKernelGGL((group_kernel<E, T, 1, NT>), g, b, 0, st, a);
+  else if (lam == 2) hipLaunchKernelGGL((group_kernel<E, T, 2, NT>), g, b, 0, st, a);
+  else hipLaunchKernelGGL((group_kernel<E, T, 3, NT>), g, b, 0, st, a);
 }
 
 void launch_group(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st) {
   if (eb == 4) {
-    if (group_tile_u32() == 2048) launch_group_t<uint32_t, 2048>(a, lam, grid, st);
-    else launch_group_t<uint32_t, 4096>(a, lam, grid, st);
+    if (group_tile_u32() == 2048) launch_group_t<uint32_t, 2048, 256>(a, lam, grid, st);
+    else launch_group_t<uint32_t, 4096, 512>(a, lam, grid, st);
   } else if (eb == 8) {
-    launch_group_t<uint64_t, 2048>(a, lam, grid, st);
+    launch_group_t<uint64_t, 2048, 256>(a, lam, grid, st);
   } else {
-    launch_group_t<uint4, 1024>(a, lam, grid, st);
+    launch_group_t<uint4, 1024, 256>(a, lam, grid, st);
   }
 }
 
