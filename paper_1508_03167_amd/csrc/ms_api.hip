@@ -64,7 +64,7 @@ constexpr uint32_t kDefaultB = 4096;
 // planner
 // ---------------------------------------------------------------------------
 struct Layout {
-  size_t zloc, ctot, zc, P, side, kcnt, toff, tail_src, bcnt, bfill, boff, part, pool_x, pool_step, pool_src,
+  size_t zloc, ctot, zc, zg, P, side, kcnt, toff, tail_src, bcnt, bfill, boff, part, pool_x, pool_step, pool_src,
       tail_xsrc, pool_xsrc, bnd;
   size_t bytes;
 };
@@ -206,6 +206,7 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
   y.zloc = take(chunks * 256 * 2);
   y.ctot = take(chunks * 4);
   y.zc = take(chunks * 4);
+  y.zg = take((chunks + 1) * 4);
   y.P = take(merges * 4);
   y.side = take(merges);
   y.kcnt = take(merges * 4);
@@ -214,7 +215,7 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
   y.bcnt = take(buckets * 4);
   y.bfill = take(buckets * 4);
   y.boff = take((buckets + 1) * 4);
-  y.part = take(((std::max(buckets, merges) + 2047) / 2048 + 1) * 4);
+  y.part = take(((std::max(std::max(buckets, merges), chunks) + 2047) / 2048 + 1) * 4);
   y.pool_x = take(cap * 4);
   y.pool_step = take(cap * 4);
   y.pool_src = take(cap * 4);
@@ -338,6 +339,7 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
     pa.zloc = reinterpret_cast<uint16_t*>(b + y.zloc);
     pa.ctot = reinterpret_cast<uint32_t*>(b + y.ctot);
     pa.zc = reinterpret_cast<uint32_t*>(b + y.zc);
+    pa.zg = reinterpret_cast<uint32_t*>(b + y.zg);
     pa.P = reinterpret_cast<uint32_t*>(b + y.P);
     pa.side = reinterpret_cast<uint8_t*>(b + y.side);
     pa.kcnt = reinterpret_cast<uint32_t*>(b + y.kcnt);

@@ -116,62 +116,65 @@ __device__ __forceinline__ uint32_t locate_in_chunk(const PlanArgs& pa, uint64_t
 // ---------------------------------------------------------------------------
 // 2. per merge: chunk prefix, break step P and the side that ran out
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) plan_merge_kernel(PlanArgs pa) {
-  __shared__ uint32_t tmp[8];
-  __shared__ uint32_t bestA, bestB, resA, resB;
-  const uint64_t gm = blockIdx.x;
-  const int l = level_of_merge(pa, gm);
-  const HbmLevel& lv = pa.lev[l];
-  const uint32_t m = (uint32_t)(gm - lv.merge_base);
-  const uint32_t L = lv.L;
-  const MergeGeom g = merge_geom(pa, L, m);
-  const uint64_t cbase = lv.chunk_base + (uint64_t)m * lv.cpm;
-  if (threadIdx.x == 0) {
-    bestA = kNone32;
-    bestB = kNone32;
-  }
-  uint32_t running = 0;
-  for (uint32_t b = 0; b < lv.cpm; b += 256) {
-    const uint32_t idx = b + threadIdx.x;
-    const uint32_t v = idx < lv.cpm ? pa.ctot[cbase + idx] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan<256>(v, tmp, &tot);
-    if (idx < lv.cpm) {
-      const uint32_t z0 = running + ex;
-      pa.zc[cbase + idx] = z0;
-      // the (n1+1)-th zero / (n2+1)-th one fall in this chunk?
-      if (z0 <= g.n1 && (uint64_t)g.n1 < (uint64_t)z0 + v) atomicMin(&bestA, idx);
-      const uint64_t o0 = ((uint64_t)idx << kChunkLog) - z0;
-      const uint64_t ov = (1ull << kChunkLog) - v;
-      if (o0 <= g.n2 && g.n2 < o0 + ov) atomicMin(&bestB, idx);
+// zc of every chunk from the global prefix of chunk zero counts (sums wrap
+// modulo 2^32, but every merge's own prefix stays below 2^32)
+__global__ void __launch_bounds__(256) zc_kernel(PlanArgs pa) {
+  const uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= pa.total_chunks) return;
+  const HbmLevel& lv = pa.lev[level_of_chunk(pa, c)];
+  const uint64_t first = c - (c - lv.chunk_base) % lv.cpm;
+  pa.zc[c] = pa.zg[c] - pa.zg[first];
+}
+
+// Per merge (one thread each): the chunk holding the (n1+1)-th zero and the
+// one holding the (n2+1)-th one by binary search over the chunk prefixes,
+// the flip inside it, and so the break step P and the side that ran out.
+__global__ void __launch_bounds__(256) plan_break_kernel(PlanArgs pa) {
+  __shared__ uint64_t red[4];
+  const uint64_t gm = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  uint64_t used = 0;
+  if (gm < pa.total_merges) {
+    const int l = level_of_merge(pa, gm);
+    const HbmLevel& lv = pa.lev[l];
+    const uint32_t m = (uint32_t)(gm - lv.merge_base);
+    const MergeGeom g = merge_geom(pa, lv.L, m);
+    const uint64_t cb = lv.chunk_base + (uint64_t)m * lv.cpm;
+    uint32_t lo = 0, hi = lv.cpm - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (pa.zc[cb + mid] <= g.n1) lo = mid; else hi = mid - 1;
     }
-    running += tot;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    resA = kNone32;
-    if (bestA != kNone32)
-      resA = locate_in_chunk(pa, cbase + bestA, bestA, m, L, g.n1 - pa.zc[cbase + bestA], 0);
-  }
-  if (threadIdx.x == 64) {
-    resB = kNone32;
-    if (bestB != kNone32) {
-      const uint32_t o0 = (bestB << kChunkLog) - pa.zc[cbase + bestB];
-      resB = locate_in_chunk(pa, cbase + bestB, bestB, m, L, g.n2 - o0, 1);
+    uint32_t resA = kNone32;
+    {
+      const uint32_t z0 = pa.zc[cb + lo];
+      if (z0 <= g.n1 && g.n1 < z0 + pa.ctot[cb + lo]) resA = locate_in_chunk(pa, cb + lo, lo, m, lv.L, g.n1 - z0, 0);
     }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
+    lo = 0;
+    hi = lv.cpm - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (((uint64_t)mid << kChunkLog) - pa.zc[cb + mid] <= g.n2) lo = mid; else hi = mid - 1;
+    }
+    uint32_t resB = kNone32;
+    {
+      const uint64_t o0 = ((uint64_t)lo << kChunkLog) - pa.zc[cb + lo];
+      const uint64_t ov = (1ull << kChunkLog) - pa.ctot[cb + lo];
+      if (o0 <= g.n2 && g.n2 < o0 + ov) resB = locate_in_chunk(pa, cb + lo, lo, m, lv.L, (uint32_t)(g.n2 - o0), 1);
+    }
     const uint32_t P = resA < resB ? resA : resB;
     pa.P[gm] = P;
     pa.side[gm] = resA < resB ? 0 : 1;
     pa.kcnt[gm] = g.N - P;
-    atomicAdd(pa.bits, (unsigned long long)P + 1ull);
+    used = (uint64_t)P + 1;
   }
-  const uint64_t bb = lv.bucket_base + (uint64_t)m * lv.bpm;
-  for (uint32_t b = threadIdx.x; b < lv.bpm; b += 256) {
-    pa.bcnt[bb + b] = 0;
-    pa.bfill[bb + b] = 0;
+  const uint64_t t = block_sum_u64<256>(used, red);
+  if (threadIdx.x == 0 && t) atomicAdd(pa.bits, (unsigned long long)t);
+}
+
+__global__ void __launch_bounds__(256) zero2_kernel(uint32_t* a, uint32_t* b, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    a[i] = 0;
+    b[i] = 0;
   }
 }
 
@@ -511,7 +514,11 @@ __global__ void __launch_bounds__(256) bounds_kernel(PlanArgs pa) {
 void launch_plan(const PlanArgs& pa, hipStream_t st) {
   if (pa.nlev == 0) return;
   hipLaunchKernelGGL(plan_count_kernel, dim3((uint32_t)pa.total_chunks), dim3(256), 0, st, pa);
-  hipLaunchKernelGGL(plan_merge_kernel, dim3((uint32_t)pa.total_merges), dim3(256), 0, st, pa);
+  launch_scan(pa.ctot, pa.total_chunks, pa.part, pa.zg, ~0ull, pa.status, 0u, st);
+  hipLaunchKernelGGL(zc_kernel, dim3((uint32_t)((pa.total_chunks + 255) / 256)), dim3(256), 0, st, pa);
+  hipLaunchKernelGGL(plan_break_kernel, dim3((uint32_t)((pa.total_merges + 255) / 256)), dim3(256), 0, st, pa);
+  hipLaunchKernelGGL(zero2_kernel, dim3((uint32_t)std::min<uint64_t>((pa.total_buckets + 255) / 256, 4096)), dim3(256), 0,
+                     st, pa.bcnt, pa.bfill, pa.total_buckets);
   launch_scan(pa.kcnt, pa.total_merges, pa.part, pa.toff, pa.tail_cap, pa.status, 2u, st);
   hipLaunchKernelGGL(tail_count_kernel, dim3((uint32_t)pa.total_tail_wgs), dim3(256), 0, st, pa);
   launch_scan(pa.bcnt, pa.total_buckets, pa.part, pa.boff, pa.pool_cap, pa.status, 1u, st);

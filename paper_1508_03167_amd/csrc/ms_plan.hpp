@@ -71,6 +71,7 @@ struct PlanArgs {
   uint16_t* zloc;         // per granule: zeros before it within its chunk
   uint32_t* ctot;         // per chunk: zeros in the chunk
   uint32_t* zc;           // per chunk: zeros before it within its merge
+  uint32_t* zg;           // per chunk (+1): zeros before it over all chunks (modulo 2^32)
   uint32_t* P;            // per merge: break step (coin-flip prefix length)
   uint8_t* side;          // per merge: 0 = A ran out first, 1 = B ran out first
   uint32_t* kcnt;         // per merge: insertion steps N - P
