@@ -118,8 +118,13 @@ __device__ __forceinline__ uint32_t locate_in_chunk(const PlanArgs& pa, uint64_t
 // ---------------------------------------------------------------------------
 // zc of every chunk from the global prefix of chunk zero counts (sums wrap
 // modulo 2^32, but every merge's own prefix stays below 2^32)
+// (and clears the bucket counters for the insertion-loop kernels)
 __global__ void __launch_bounds__(256) zc_kernel(PlanArgs pa) {
   const uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c < pa.total_buckets) {
+    pa.bcnt[c] = 0;
+    pa.bfill[c] = 0;
+  }
   if (c >= pa.total_chunks) return;
   const HbmLevel& lv = pa.lev[level_of_chunk(pa, c)];
   const uint64_t first = c - (c - lv.chunk_base) % lv.cpm;
@@ -169,13 +174,6 @@ __global__ void __launch_bounds__(256) plan_break_kernel(PlanArgs pa) {
   }
   const uint64_t t = block_sum_u64<256>(used, red);
   if (threadIdx.x == 0 && t) atomicAdd(pa.bits, (unsigned long long)t);
-}
-
-__global__ void __launch_bounds__(256) zero2_kernel(uint32_t* a, uint32_t* b, uint64_t n) {
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
-    a[i] = 0;
-    b[i] = 0;
-  }
 }
 
 __device__ __forceinline__ uint32_t tail_draw(const PlanArgs& pa, uint32_t L, uint32_t m, uint32_t i,
@@ -287,8 +285,44 @@ __global__ void __launch_bounds__(256) scan_down_kernel(const uint32_t* __restri
   }
 }
 
+// The same scan by one workgroup, for short arrays (one launch instead of three).
+constexpr uint64_t kScanOneMax = 65536;
+__global__ void __launch_bounds__(1024) scan_one_kernel(const uint32_t* __restrict__ in, uint64_t count,
+                                                        uint32_t* __restrict__ out, uint64_t cap, uint32_t* status,
+                                                        uint32_t flag) {
+  __shared__ uint32_t tmp[20];
+  constexpr int K = 8;
+  uint32_t running = 0;
+  for (uint64_t b0 = 0; b0 < count; b0 += 1024 * K) {
+    const uint64_t base = b0 + (uint64_t)threadIdx.x * K;
+    uint32_t v[K];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      v[k] = base + k < count ? in[base + k] : 0u;
+      sum += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = running + block_excl_scan<1024>(sum, tmp, &tot);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (base + k < count) out[base + k] = run;
+      run += v[k];
+    }
+    running += tot;
+  }
+  if (threadIdx.x == 0) {
+    out[count] = running;
+    if ((uint64_t)running > cap) atomicOr(status, flag);
+  }
+}
+
 static void launch_scan(const uint32_t* in, uint64_t count, uint32_t* part, uint32_t* out, uint64_t cap,
                         uint32_t* status, uint32_t flag, hipStream_t st) {
+  if (count <= kScanOneMax) {
+    hipLaunchKernelGGL(scan_one_kernel, dim3(1), dim3(1024), 0, st, in, count, out, cap, status, flag);
+    return;
+  }
   const uint32_t nparts = (uint32_t)((count + kScanPer - 1) / kScanPer);
   hipLaunchKernelGGL(scan_reduce_kernel, dim3(nparts), dim3(256), 0, st, in, count, part);
   hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, st, part, nparts, out + count, cap, status, flag);
@@ -431,8 +465,8 @@ __device__ __forceinline__ uint32_t trace_to_input(const PlanArgs& pa, int l, ui
   return (uint32_t)(abs - s0);
 }
 
-__global__ void __launch_bounds__(256) trace_kernel(PlanArgs pa) {
-  const TailWg t = tail_wg(pa, blockIdx.x);
+__device__ __forceinline__ void trace_body(const PlanArgs& pa, uint64_t wg) {
+  const TailWg t = tail_wg(pa, wg);
   const int l = t.l;
   const uint64_t toff = pa.toff[t.gm];
   for (uint32_t d = t.w * 256 + threadIdx.x; d < t.k; d += t.lv->wpm * 256) {
@@ -472,8 +506,7 @@ __device__ __forceinline__ uint32_t rank_at(const PlanArgs& pa, int l, uint32_t 
 // One thread per boundary record: the window tree at slot b*T of top merge M
 // (node 0 = the top window's start; a node's children start at its rank in
 // the left half and at its slot minus its rank in the right half).
-__global__ void __launch_bounds__(256) bounds_kernel(PlanArgs pa) {
-  const uint64_t idx = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void bounds_body(const PlanArgs& pa, uint64_t idx) {
   if (idx >= pa.total_bnd) return;
   int g = (int)pa.ngroup - 1;
   while (g > 0 && pa.grp[g].bnd_first > idx) --g;
@@ -511,23 +544,28 @@ __global__ void __launch_bounds__(256) bounds_kernel(PlanArgs pa) {
 // ---------------------------------------------------------------------------
 // host launcher
 // ---------------------------------------------------------------------------
+// The trace (one workgroup per insertion-loop workgroup) and the boundary
+// records (one thread each) in one launch.
+__global__ void __launch_bounds__(256) trace_bounds_kernel(PlanArgs pa) {
+  if (blockIdx.x < pa.total_tail_wgs) trace_body(pa, blockIdx.x);
+  else bounds_body(pa, (blockIdx.x - pa.total_tail_wgs) * 256 + threadIdx.x);
+}
+
 void launch_plan(const PlanArgs& pa, hipStream_t st) {
   if (pa.nlev == 0) return;
   hipLaunchKernelGGL(plan_count_kernel, dim3((uint32_t)pa.total_chunks), dim3(256), 0, st, pa);
   launch_scan(pa.ctot, pa.total_chunks, pa.part, pa.zg, ~0ull, pa.status, 0u, st);
-  hipLaunchKernelGGL(zc_kernel, dim3((uint32_t)((pa.total_chunks + 255) / 256)), dim3(256), 0, st, pa);
+  hipLaunchKernelGGL(zc_kernel, dim3((uint32_t)((std::max(pa.total_chunks, pa.total_buckets) + 255) / 256)), dim3(256),
+                     0, st, pa);
   hipLaunchKernelGGL(plan_break_kernel, dim3((uint32_t)((pa.total_merges + 255) / 256)), dim3(256), 0, st, pa);
-  hipLaunchKernelGGL(zero2_kernel, dim3((uint32_t)std::min<uint64_t>((pa.total_buckets + 255) / 256, 4096)), dim3(256), 0,
-                     st, pa.bcnt, pa.bfill, pa.total_buckets);
   launch_scan(pa.kcnt, pa.total_merges, pa.part, pa.toff, pa.tail_cap, pa.status, 2u, st);
   hipLaunchKernelGGL(tail_count_kernel, dim3((uint32_t)pa.total_tail_wgs), dim3(256), 0, st, pa);
   launch_scan(pa.bcnt, pa.total_buckets, pa.part, pa.boff, pa.pool_cap, pa.status, 1u, st);
   hipLaunchKernelGGL(tail_scatter_kernel, dim3((uint32_t)pa.total_tail_wgs), dim3(256), 0, st, pa);
   hipLaunchKernelGGL(tail_resolve_kernel, dim3((uint32_t)pa.total_tail_wgs), dim3(256), 0, st, pa);
-  if (pa.tail_xsrc) {
-    hipLaunchKernelGGL(trace_kernel, dim3((uint32_t)pa.total_tail_wgs), dim3(256), 0, st, pa);
-    hipLaunchKernelGGL(bounds_kernel, dim3((uint32_t)((pa.total_bnd + 255) / 256)), dim3(256), 0, st, pa);
-  }
+  if (pa.tail_xsrc)
+    hipLaunchKernelGGL(trace_bounds_kernel, dim3((uint32_t)(pa.total_tail_wgs + (pa.total_bnd + 255) / 256)), dim3(256),
+                       0, st, pa);
 }
 
 }  // namespace ms
