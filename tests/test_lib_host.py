@@ -58,6 +58,20 @@ def test_rejects_bad_arguments_without_a_device():
     assert b"cutoff" in L.ms_last_error()
     assert L.ms_shuffle_batched(None, None, 3, 1, None) == -1
     assert L.ms_shuffle_batched(None, None, 0, 1, None) == 0
+    # batched: every array is checked before anything runs, and the message names it
+    vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    ptrs = (vp * 3)(16, None, 32)
+    sizes = (u64 * 3)(10, 5, 7)
+    assert L.ms_shuffle_batched(ptrs, sizes, 3, 1, None) == -1
+    assert b"array 1" in L.ms_last_error()
+    ptrs = (vp * 3)(16, 32, 36)
+    ebs = (u32 * 3)(4, 8, 8)
+    assert L.ms_shuffle_batched_ex(ptrs, sizes, ebs, 3, 1, None, None, None) == -1   # 36 not 8-aligned
+    assert b"array 2" in L.ms_last_error()
+    ebs = (u32 * 3)(4, 8, 12)
+    assert L.ms_shuffle_batched_ex(ptrs, sizes, ebs, 3, 1, None, None, None) == -2   # element size
+    sizes = (u64 * 3)(10, 1 << 33, 7)
+    assert L.ms_shuffle_batched(ptrs, sizes, 3, 1, None) == -2                       # n too large
     info = M._lib.MSPlanInfo()
     assert L.ms_plan(10, 3, None, ctypes.byref(info)) == -2
     assert L.ms_scratch_bytes(1 << 20, 4) > 4 << 20
