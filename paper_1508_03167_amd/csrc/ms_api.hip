@@ -232,6 +232,7 @@ uint64_t scratch_of(const HostPlan& hp) { return (hp.nlev ? hp.n * hp.eb : 0) + 
 // per-device context and per-stream scratch
 // ---------------------------------------------------------------------------
 struct Arena {
+  std::mutex mu;          // held for a whole call's launch sequence on this stream
   void* data = nullptr;   // array copy
   size_t data_bytes = 0;
   void* plan = nullptr;   // plan tables
@@ -262,6 +263,7 @@ struct ProfRec {
 };
 bool g_prof = false;
 std::vector<ProfRec> g_prof_recs;
+std::mutex g_prof_mu;
 
 int device_ctx(DeviceCtx** out) {
   int dev = 0;
@@ -309,6 +311,7 @@ struct ProfScope {
   ~ProfScope() {
     if (!a) return;
     (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_recs.push_back({cls, a, b});
   }
 };
@@ -321,10 +324,16 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
   if (n > 0 && ptr == nullptr) return fail(MS_ERR_INVALID, "null pointer with n = %llu", (unsigned long long)n);
   if (((uintptr_t)ptr) % eb != 0) return fail(MS_ERR_INVALID, "pointer not aligned to %u bytes", eb);
   if (n <= 1) return MS_OK;
-  std::lock_guard<std::mutex> lk(g_mu);
   DeviceCtx* dc;
-  if ((rc = device_ctx(&dc))) return rc;
-  Arena& ar = dc->arenas[st];
+  Arena* arp;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if ((rc = device_ctx(&dc))) return rc;
+    arp = &dc->arenas[st];  // map nodes do not move
+  }
+  // the stream's scratch is this call's until its launches are queued
+  std::lock_guard<std::mutex> alk(arp->mu);
+  Arena& ar = *arp;
   if ((rc = ensure(&ar.data, &ar.data_bytes, hp.nlev ? n * eb : 0, st))) return rc;
   if ((rc = ensure(&ar.plan, &ar.plan_bytes, hp.lay.bytes, st))) return rc;
   unsigned long long* bits = d_bits ? d_bits : dc->dummy_bits;
