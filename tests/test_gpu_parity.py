@@ -142,3 +142,21 @@ def test_repeat_calls_deterministic(M):
     a, ab = gpu_perm(M, 300007, 8)
     b, bb = gpu_perm(M, 300007, 8)
     assert np.array_equal(a, b) and ab == bb
+
+
+@pytest.mark.parametrize("off", [1, 2, 3])
+@pytest.mark.parametrize("n", [70001, 300007])
+def test_views_not_16_byte_aligned(M, n, off):
+    # 4-byte aligned but not 16-byte aligned arrays take the scalar staging path
+    import torch
+
+    _say(f"[gpu] unaligned view n={n} off={off}")
+    base = torch.zeros(n + 4, dtype=torch.int32, device="cuda")
+    x = base[off:off + n]
+    x.copy_(torch.arange(n, dtype=torch.int32, device="cuda"))
+    bits = torch.zeros(1, dtype=torch.int64, device="cuda")
+    M.shuffle_(x, 17, bits=bits)
+    want, wbits = O.permutation(n, 4096, 17)
+    assert np.array_equal(x.cpu().numpy().view(np.uint32), want)
+    assert int(bits.item()) == wbits
+    assert int(base[:off].abs().sum().item()) == 0 and int(base[off + n:].abs().sum().item()) == 0
