@@ -152,7 +152,7 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
   }
   // fused passes: groups of at most 3 consecutive HBM levels, sizes within one
   uint32_t lpp = cfg && cfg->levels_per_pass ? cfg->levels_per_pass : 3u;
-  if (lpp > 3) lpp = 3;
+  if (lpp > (uint32_t)kGroupMax) lpp = kGroupMax;
   static const bool old_pass = [] {
     const char* e = getenv("MS_OLD_PASS");
     return e && atoi(e) != 0;

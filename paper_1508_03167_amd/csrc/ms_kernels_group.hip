@@ -427,7 +427,8 @@ static void launch_group_t(const GroupArgs& a, int lam, uint64_t tiles, hipStrea
   const dim3 g((uint32_t)tiles), b(NT);
   if (lam == 1) hipLaunchKernelGGL((group_kernel<E, T, 1, NT>), g, b, 0, st, a);
   else if (lam == 2) hipLaunchKernelGGL((group_kernel<E, T, 2, NT>), g, b, 0, st, a);
-  else hipLaunchKernelGGL((group_kernel<E, T, 3, NT>), g, b, 0, st, a);
+  else if (lam == 3) hipLaunchKernelGGL((group_kernel<E, T, 3, NT>), g, b, 0, st, a);
+  else hipLaunchKernelGGL((group_kernel<E, T, 4, NT>), g, b, 0, st, a);
 }
 
 void launch_group(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st) {

@@ -517,16 +517,17 @@ __device__ __forceinline__ void bounds_body(const PlanArgs& pa, uint64_t idx) {
   const int lt = (int)(gi.lf + gi.lam - 1);
   const MergeGeom gt = merge_geom(pa, pa.lev[lt].L, M);
   const int nodes = (1 << gi.lam) - 1;
-  uint32_t u[7], ra[7];
+  constexpr int KN = (1 << kGroupMax) - 1;
+  uint32_t u[KN], ra[KN];
   u[0] = (uint32_t)min((uint64_t)b * gi.T, (uint64_t)gt.N);
 #pragma unroll
-  for (int k = 0; k < 7; ++k) {
+  for (int k = 0; k < KN; ++k) {
     if (k < nodes) {
       const int d = 31 - __clz(k + 1);
       const int l = lt - d;
       const uint32_t m = (M << d) + (uint32_t)(k - ((1 << d) - 1));
       ra[k] = rank_at(pa, l, m, u[k]);
-      if (2 * k + 2 < 7 && 2 * k + 2 < nodes) {
+      if (2 * k + 2 < KN && 2 * k + 2 < nodes) {
         u[2 * k + 1] = ra[k];
         u[2 * k + 2] = u[k] - ra[k];
       }
@@ -534,7 +535,7 @@ __device__ __forceinline__ void bounds_body(const PlanArgs& pa, uint64_t idx) {
   }
   uint32_t* rec = pa.bnd + idx * kBndStride;
 #pragma unroll
-  for (int k = 0; k < 7; ++k)
+  for (int k = 0; k < KN; ++k)
     if (k < nodes) {
       rec[2 * k] = u[k];
       rec[2 * k + 1] = ra[k];

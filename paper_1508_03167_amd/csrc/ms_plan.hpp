@@ -18,7 +18,7 @@
 namespace ms {
 
 constexpr int kMaxLevels = 32;
-constexpr int kGroupMax = 3;           // merge levels fused into one HBM pass, at most
+constexpr int kGroupMax = 4;           // merge levels fused into one HBM pass, at most
 constexpr uint32_t kGranLog = 7;       // 128 flips per granule (one Philox block)
 constexpr uint32_t kChunkGranLog = 8;  // 256 granules per chunk
 constexpr uint32_t kChunkLog = kGranLog + kChunkGranLog;  // 32768 flips per chunk
@@ -152,7 +152,6 @@ struct GroupArgs {
   uint32_t L[kGroupMax];
   uint32_t blog[kGroupMax];
   uint32_t bpm[kGroupMax];
-  uint32_t pad2;
   uint64_t merge_base[kGroupMax];
   uint64_t bucket_base[kGroupMax];
 };

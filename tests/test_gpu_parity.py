@@ -84,8 +84,9 @@ def test_result_independent_of_lds_levels(M, n):
 def test_result_independent_of_levels_per_pass(M, n, B):
     _say(f"[gpu] levels-per-pass variants n={n} B={B}")
     want, wbits = O.permutation(n, B, 11)
-    for kw in ({"levels_per_pass": 1}, {"levels_per_pass": 2}, {"levels_per_pass": 3},
-               {"levels_per_pass": 2, "hbm_only": True}, {"levels_per_pass": 3, "hbm_only": True}):
+    for kw in ({"levels_per_pass": 1}, {"levels_per_pass": 2}, {"levels_per_pass": 3}, {"levels_per_pass": 4},
+               {"levels_per_pass": 2, "hbm_only": True}, {"levels_per_pass": 3, "hbm_only": True},
+               {"levels_per_pass": 4, "hbm_only": True}):
         got, gbits = gpu_perm(M, n, 11, leaf_B=B, **kw)
         assert np.array_equal(got, want), (kw, int(np.argmax(got != want)))
         assert gbits == wbits, kw
