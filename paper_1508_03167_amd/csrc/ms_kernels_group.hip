@@ -308,6 +308,7 @@ __global__ void __launch_bounds__(NT) group_kernel(GroupArgs a) {
   // before the break step, a zero flip takes A[z] (at off + z) and a one
   // takes B[t - u0 - z] (at bdelta + t - z), z = zeros in [u0, t) = the
   // wpre-based count minus zbase; from the break step on, t maps to t + pdelta.
+  // lim = min(u1, P): a group of 4 slots below it takes the short path.
   // gpre: groups of 4 slots in the windows before it on its level.
   if (tid < NODES) {
     const Win& w = win[tid];
@@ -320,7 +321,7 @@ __global__ void __launch_bounds__(NT) group_kernel(GroupArgs a) {
     const uint32_t pdelta = w.side == 0 ? w.off + la4 - w.n1 - w.u0 + w.ra0 : w.off - w.n2 - w.ra0;
     uint32_t gpre = 0;
     for (int q = (1 << d) - 1; q < tid; ++q) gpre += (win[q].u1 - win[q].u0 + 3u) >> 2;
-    *reinterpret_cast<uint4*>(&hot[tid][0]) = make_uint4(w.u0 - w.off, w.P, wbase, zbase);
+    *reinterpret_cast<uint4*>(&hot[tid][0]) = make_uint4(w.u0 - w.off, min(w.u1, w.P), wbase, zbase);
     *reinterpret_cast<uint4*>(&hot[tid][4]) = make_uint4(w.off, w.off + la4 - w.u0, pdelta, gpre);
     if (tid == (2 << d) - 2) lgroups[LAM - 1 - d] = gpre + ((w.u1 - w.u0 + 3u) >> 2);
   }
@@ -332,29 +333,46 @@ __global__ void __launch_bounds__(NT) group_kernel(GroupArgs a) {
 #pragma unroll
   for (int li = 0; li < LAM; ++li) {
     const int d = LAM - 1 - li;
-    const int kf = (1 << d) - 1, kl = (2 << d) - 1;
+    const int kf = (1 << d) - 1;
     const E* src = buf[li & 1];
     E* dst = buf[(li + 1) & 1];
     const uint32_t ng = lgroups[li];
     for (uint32_t g = tid; g < ng; g += NT) {
       int k = kf;
-      while (k + 1 < kl && g >= hot[k + 1][7]) ++k;
+#pragma unroll
+      for (int q = 1; q < (1 << d); ++q) k += g >= hot[kf + q][7] ? 1 : 0;
       const uint4 h0 = *reinterpret_cast<const uint4*>(&hot[k][0]);
       const uint4 h1 = *reinterpret_cast<const uint4*>(&hot[k][4]);
       const uint32_t s0 = h1.x + 4 * (g - h1.w);
       const uint32_t t0 = s0 + h0.x;
       const uint32_t wi = min(h0.z + (t0 >> 5), (uint32_t)NWORD - 2);
       const uint32_t wlo = words[wi], whi = words[wi + 1];
-      uint32_t z = wpre[wi] - h0.w + (uint32_t)__popc(~wlo & ((1u << (t0 & 31)) - 1u));
+      const uint32_t z0 = wpre[wi] - h0.w + (uint32_t)__popc(~wlo & ((1u << (t0 & 31)) - 1u));
       const uint32_t bits4 = (uint32_t)((((uint64_t)whi << 32) | wlo) >> (t0 & 31));
       uint32_t fr[4];
+      if (t0 + 4 <= h0.y) {
+        // four slots of the window before the break step: with o_j the ones
+        // among the first j flips, slot j takes B at bb + o_j or A at
+        // ab + j - o_j
+        const uint32_t ab = h1.x + z0, bb = h1.y + t0 - z0;
+        uint32_t o = 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint32_t t = t0 + j;
-        const uint32_t bit = (bits4 >> j) & 1u;
-        const uint32_t rk = bit ? h1.y + t - z : h1.x + z;
-        fr[j] = min(t < h0.y ? rk : t + h1.z, (uint32_t)TB - 1);
-        z += bit ^ 1u;
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t bit = (bits4 >> j) & 1u;
+          fr[j] = bit ? bb + o : ab + j - o;
+          o += bit;
+        }
+      } else {
+        const uint32_t P = win[k].P;
+        uint32_t z = z0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t t = t0 + j;
+          const uint32_t bit = (bits4 >> j) & 1u;
+          const uint32_t rk = bit ? h1.y + t - z : h1.x + z;
+          fr[j] = min(t < P ? rk : t + h1.z, (uint32_t)TB - 1);
+          z += bit ^ 1u;
+        }
       }
       if constexpr (sizeof(E) == 4) {
         uint4 o;
