@@ -354,7 +354,9 @@ __global__ void __launch_bounds__(NT) group_kernel(GroupArgs a) {
         // four slots of the window before the break step: with o_j the ones
         // among the first j flips, slot j takes B at bb + o_j or A at
         // ab + j - o_j
-        const uint32_t ab = h1.x + z0, bb = h1.y + t0 - z0;
+        uint32_t ab = h1.x + z0, bb = h1.y + t0 - z0;
+        // one value each (kept from being re-expanded per slot)
+        asm volatile("" : "+v"(ab), "+v"(bb));
         uint32_t o = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
