@@ -80,10 +80,14 @@ typedef struct ms_config {
                                clamped to 1..4; the passes split the levels as evenly as
                                possible */
   uint32_t lds_levels_max;  /* cap on merge levels run in LDS by the leaf kernel; 0 = as many as fit */
-  uint32_t flags;           /* MS_CFG_HBM_ONLY: run every merge level as an HBM pass */
+  uint32_t flags;           /* MS_CFG_HBM_ONLY: run every merge level as an HBM pass;
+                               MS_CFG_ONE_LEVEL_PASSES: one streaming pass plus one patch
+                               kernel per HBM level instead of fused passes (levels_per_pass
+                               is then ignored) */
 } ms_config;
 
 #define MS_CFG_HBM_ONLY 1u
+#define MS_CFG_ONE_LEVEL_PASSES 2u
 
 /* Shuffle n elements of elem_bytes bytes at dev_ptr in place (Algorithm
  * MergeShuffle with cutoff 4096), seed as above, on stream. */

@@ -150,14 +150,11 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
     cap += lcap;
     tiles = std::max<uint64_t>(tiles, (uint64_t)lv.nmerge * lv.tpm);
   }
-  // fused passes: groups of at most 3 consecutive HBM levels, sizes within one
+  // fused passes: groups of at most 3 consecutive HBM levels (by default),
+  // sizes within one; or one streaming pass and one patch kernel per level
   uint32_t lpp = cfg && cfg->levels_per_pass ? cfg->levels_per_pass : 3u;
   if (lpp > (uint32_t)kGroupMax) lpp = kGroupMax;
-  static const bool old_pass = [] {
-    const char* e = getenv("MS_OLD_PASS");
-    return e && atoi(e) != 0;
-  }();
-  hp.fused = !old_pass;
+  hp.fused = !(cfg && (cfg->flags & MS_CFG_ONE_LEVEL_PASSES));
   if (!hp.fused) lpp = 1;
   hp.ngroup = hp.nlev ? (hp.nlev + lpp - 1) / lpp : 0;
   {

@@ -86,7 +86,8 @@ def test_result_independent_of_levels_per_pass(M, n, B):
     want, wbits = O.permutation(n, B, 11)
     for kw in ({"levels_per_pass": 1}, {"levels_per_pass": 2}, {"levels_per_pass": 3}, {"levels_per_pass": 4},
                {"levels_per_pass": 2, "hbm_only": True}, {"levels_per_pass": 3, "hbm_only": True},
-               {"levels_per_pass": 4, "hbm_only": True}):
+               {"levels_per_pass": 4, "hbm_only": True}, {"one_level_passes": True},
+               {"one_level_passes": True, "hbm_only": True}):
         got, gbits = gpu_perm(M, n, 11, leaf_B=B, **kw)
         assert np.array_equal(got, want), (kw, int(np.argmax(got != want)))
         assert gbits == wbits, kw
@@ -161,3 +162,24 @@ def test_views_not_16_byte_aligned(M, n, off):
     assert np.array_equal(x.cpu().numpy().view(np.uint32), want)
     assert int(bits.item()) == wbits
     assert int(base[:off].abs().sum().item()) == 0 and int(base[off + n:].abs().sum().item()) == 0
+
+
+def test_allocation_failure_is_reported(M):
+    # the library's scratch allocation refused (test hook): the call fails
+    # cleanly with MS_ERR_NOMEM and leaves the array untouched
+    import subprocess
+
+    code = (
+        "import sys, torch; sys.path.insert(0, %r)\n"
+        "import paper_1508_03167_amd as M\n"
+        "x = torch.arange(1 << 20, dtype=torch.int32, device='cuda')\n"
+        "try:\n"
+        "    M.shuffle_(x, 1)\n"
+        "    print('no error')\n"
+        "except M.MSError as e:\n"
+        "    torch.cuda.synchronize()\n"
+        "    ok = bool(torch.equal(x, torch.arange(1 << 20, dtype=torch.int32, device='cuda')))\n"
+        "    print('code', e.code, 'untouched', ok)\n" % os.path.dirname(HERE))
+    env = dict(os.environ, MS_FAIL_ALLOC="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert "code -3 untouched True" in r.stdout, (r.stdout, r.stderr[-2000:])
