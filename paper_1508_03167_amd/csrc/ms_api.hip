@@ -10,6 +10,7 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -25,6 +26,11 @@ namespace ms {
 void launch_group(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st);
 int group_tile(uint32_t eb);
 void launch_plan(const PlanArgs& pa, hipStream_t st);
+void launch_plan_batch(const PlanArgs* d_pas, uint32_t count, hipStream_t st);
+void launch_leaf_multi(const LeafArgs* jobs, const uint32_t* wpre, uint32_t njobs, uint32_t nwg, uint32_t eb,
+                       hipStream_t st);
+void launch_group_multi(const GroupArgs* jobs, const uint32_t* tpre, uint32_t njobs, uint32_t ntiles, int lam,
+                        uint32_t eb, hipStream_t st);
 void launch_leaf(const LeafArgs& a, uint32_t eb, bool ident, uint64_t grid, hipStream_t st);
 void launch_leaf_batch(const LeafBatch& jb, uint32_t njobs, uint32_t eb, hipStream_t st);
 void launch_merge_pass(const PassArgs& a, uint32_t eb, uint64_t grid, hipStream_t st);
@@ -234,6 +240,15 @@ struct Arena {
   size_t data_bytes = 0;
   void* plan = nullptr;   // plan tables
   size_t plan_bytes = 0;
+  // batched calls: descriptors, plan tables and array copies of one wave of
+  // arrays, and two pinned staging buffers for the descriptors (each reused
+  // once the copy out of it has run)
+  void* wave = nullptr;
+  size_t wave_bytes = 0;
+  void* stage[2] = {nullptr, nullptr};
+  size_t stage_bytes[2] = {0, 0};
+  hipEvent_t stage_done[2] = {nullptr, nullptr};
+  int stage_next = 0;
 };
 
 constexpr int kSideStreams = 4;
@@ -313,6 +328,68 @@ struct ProfScope {
   }
 };
 
+// Point the plan's device arrays into a plan area of hp.lay.bytes bytes.
+void bind_plan(HostPlan& hp, void* area) {
+  PlanArgs& pa = hp.pa;
+  char* b = reinterpret_cast<char*>(area);
+  const Layout& y = hp.lay;
+  pa.zloc = reinterpret_cast<uint16_t*>(b + y.zloc);
+  pa.ctot = reinterpret_cast<uint32_t*>(b + y.ctot);
+  pa.zc = reinterpret_cast<uint32_t*>(b + y.zc);
+  pa.zg = reinterpret_cast<uint32_t*>(b + y.zg);
+  pa.P = reinterpret_cast<uint32_t*>(b + y.P);
+  pa.side = reinterpret_cast<uint8_t*>(b + y.side);
+  pa.kcnt = reinterpret_cast<uint32_t*>(b + y.kcnt);
+  pa.toff = reinterpret_cast<uint32_t*>(b + y.toff);
+  pa.tail_src = reinterpret_cast<uint32_t*>(b + y.tail_src);
+  pa.bcnt = reinterpret_cast<uint32_t*>(b + y.bcnt);
+  pa.bfill = reinterpret_cast<uint32_t*>(b + y.bfill);
+  pa.boff = reinterpret_cast<uint32_t*>(b + y.boff);
+  pa.part = reinterpret_cast<uint32_t*>(b + y.part);
+  pa.pool_x = reinterpret_cast<uint32_t*>(b + y.pool_x);
+  pa.pool_step = reinterpret_cast<uint32_t*>(b + y.pool_step);
+  pa.pool_src = reinterpret_cast<uint32_t*>(b + y.pool_src);
+  pa.tail_xsrc = hp.fused ? reinterpret_cast<uint32_t*>(b + y.tail_xsrc) : nullptr;
+  pa.pool_xsrc = hp.fused ? reinterpret_cast<uint32_t*>(b + y.pool_xsrc) : nullptr;
+  pa.bnd = hp.fused ? reinterpret_cast<uint32_t*>(b + y.bnd) : nullptr;
+}
+
+// Arguments of fused pass g, reading cur and writing other.
+GroupArgs group_args(const HostPlan& hp, uint32_t g, const void* cur, void* other) {
+  const PlanArgs& pa = hp.pa;
+  GroupArgs ga;
+  memset(&ga, 0, sizeof ga);
+  const GroupInfo& gi = pa.grp[g];
+  ga.X = cur;
+  ga.Z = other;
+  ga.n = hp.n;
+  ga.c = hp.c;
+  ga.tpm = gi.tpm;
+  ga.ntiles = (uint32_t)((uint64_t)pa.lev[gi.lf + gi.lam - 1].nmerge * gi.tpm);
+  ga.key0 = pa.key0;
+  ga.key1 = pa.key1;
+  ga.vec_ok = ((uintptr_t)cur % 16 == 0 && (uintptr_t)other % 16 == 0) ? 1u : 0u;
+  ga.P = pa.P;
+  ga.side = pa.side;
+  ga.bnd = pa.bnd + gi.bnd_first * kBndStride;
+  ga.toff = pa.toff;
+  ga.tail_xsrc = pa.tail_xsrc;
+  ga.boff = pa.boff;
+  ga.pool_x = pa.pool_x;
+  ga.pool_xsrc = pa.pool_xsrc;
+  ga.tail_cap = pa.tail_cap;
+  ga.pool_cap = pa.pool_cap;
+  for (uint32_t k = 0; k < gi.lam; ++k) {
+    const HbmLevel& lv = pa.lev[gi.lf + k];
+    ga.L[k] = lv.L;
+    ga.blog[k] = lv.blog;
+    ga.bpm[k] = lv.bpm;
+    ga.merge_base[k] = lv.merge_base;
+    ga.bucket_base[k] = lv.bucket_base;
+  }
+  return ga;
+}
+
 int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, const ms_config* cfg,
             unsigned long long* d_bits, bool ident) {
   HostPlan hp;
@@ -340,27 +417,7 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
   pa.bits = bits;
   pa.status = dc->status;
   if (hp.nlev) {
-    char* b = reinterpret_cast<char*>(ar.plan);
-    const Layout& y = hp.lay;
-    pa.zloc = reinterpret_cast<uint16_t*>(b + y.zloc);
-    pa.ctot = reinterpret_cast<uint32_t*>(b + y.ctot);
-    pa.zc = reinterpret_cast<uint32_t*>(b + y.zc);
-    pa.zg = reinterpret_cast<uint32_t*>(b + y.zg);
-    pa.P = reinterpret_cast<uint32_t*>(b + y.P);
-    pa.side = reinterpret_cast<uint8_t*>(b + y.side);
-    pa.kcnt = reinterpret_cast<uint32_t*>(b + y.kcnt);
-    pa.toff = reinterpret_cast<uint32_t*>(b + y.toff);
-    pa.tail_src = reinterpret_cast<uint32_t*>(b + y.tail_src);
-    pa.bcnt = reinterpret_cast<uint32_t*>(b + y.bcnt);
-    pa.bfill = reinterpret_cast<uint32_t*>(b + y.bfill);
-    pa.boff = reinterpret_cast<uint32_t*>(b + y.boff);
-    pa.part = reinterpret_cast<uint32_t*>(b + y.part);
-    pa.pool_x = reinterpret_cast<uint32_t*>(b + y.pool_x);
-    pa.pool_step = reinterpret_cast<uint32_t*>(b + y.pool_step);
-    pa.pool_src = reinterpret_cast<uint32_t*>(b + y.pool_src);
-    pa.tail_xsrc = hp.fused ? reinterpret_cast<uint32_t*>(b + y.tail_xsrc) : nullptr;
-    pa.pool_xsrc = hp.fused ? reinterpret_cast<uint32_t*>(b + y.pool_xsrc) : nullptr;
-    pa.bnd = hp.fused ? reinterpret_cast<uint32_t*>(b + y.bnd) : nullptr;
+    bind_plan(hp, ar.plan);
     ProfScope ps(0, st);
     launch_plan(pa, st);
   }
@@ -383,36 +440,8 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
   }
   for (uint32_t g = 0; hp.fused && g < hp.ngroup; ++g) {
     void* other = cur == X ? Y : X;
-    GroupArgs ga;
-    memset(&ga, 0, sizeof ga);
     const GroupInfo& gi = pa.grp[g];
-    ga.X = cur;
-    ga.Z = other;
-    ga.n = n;
-    ga.c = hp.c;
-    ga.tpm = gi.tpm;
-    ga.ntiles = (uint32_t)((uint64_t)pa.lev[gi.lf + gi.lam - 1].nmerge * gi.tpm);
-    ga.key0 = pa.key0;
-    ga.key1 = pa.key1;
-    ga.vec_ok = ((uintptr_t)cur % 16 == 0 && (uintptr_t)other % 16 == 0) ? 1u : 0u;
-    ga.P = pa.P;
-    ga.side = pa.side;
-    ga.bnd = pa.bnd + gi.bnd_first * kBndStride;
-    ga.toff = pa.toff;
-    ga.tail_xsrc = pa.tail_xsrc;
-    ga.boff = pa.boff;
-    ga.pool_x = pa.pool_x;
-    ga.pool_xsrc = pa.pool_xsrc;
-    ga.tail_cap = pa.tail_cap;
-    ga.pool_cap = pa.pool_cap;
-    for (uint32_t k = 0; k < gi.lam; ++k) {
-      const HbmLevel& lv = pa.lev[gi.lf + k];
-      ga.L[k] = lv.L;
-      ga.blog[k] = lv.blog;
-      ga.bpm[k] = lv.bpm;
-      ga.merge_base[k] = lv.merge_base;
-      ga.bucket_base[k] = lv.bucket_base;
-    }
+    const GroupArgs ga = group_args(hp, g, cur, other);
     const HbmLevel& top = pa.lev[gi.lf + gi.lam - 1];
     {
       ProfScope ps(2, st);
@@ -455,6 +484,202 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
   return MS_OK;
 }
 
+// Arrays of a batch that need HBM passes but hold at most kWaveMaxN
+// elements run in waves: one plan launch for the whole wave (a workgroup per
+// array), one leaf launch per element size and one launch per (fused pass,
+// element size, levels in the pass), so that the launch count does not grow
+// with the number of arrays.  Every array gets its own plan tables and array
+// copy inside the wave's scratch.
+constexpr uint64_t kWaveMaxN = 1ull << 21;
+constexpr size_t kWaveScratch = 512ull << 20;
+constexpr uint32_t kWaveMaxArrays = 4096;
+
+// Arrays per wave: kWaveMaxArrays, or fewer through MS_WAVE_ARRAYS (a tuning
+// and testing knob; the permutations do not depend on it).
+uint32_t wave_max_arrays() {
+  const char* e = getenv("MS_WAVE_ARRAYS");
+  const long v = e ? atol(e) : 0;
+  return v > 0 && v < (long)kWaveMaxArrays ? (uint32_t)v : kWaveMaxArrays;
+}
+
+bool wave_eligible(const HostPlan& hp) { return hp.nlev > 0 && hp.fused && hp.n <= kWaveMaxN; }
+
+int stage_buffer(Arena& ar, size_t bytes, void** out, int* which) {
+  const int i = ar.stage_next;
+  ar.stage_next ^= 1;
+  if (!ar.stage_done[i]) HIP_TRY(hipEventCreateWithFlags(&ar.stage_done[i], hipEventDisableTiming));
+  // the copy that last read this buffer must have run before it is rewritten
+  HIP_TRY(hipEventSynchronize(ar.stage_done[i]));
+  if (ar.stage_bytes[i] < bytes) {
+    if (ar.stage[i]) HIP_TRY(hipHostFree(ar.stage[i]));
+    ar.stage[i] = nullptr;
+    ar.stage_bytes[i] = 0;
+    if (getenv("MS_FAIL_ALLOC")) return fail(MS_ERR_NOMEM, "staging allocation of %zu bytes refused (MS_FAIL_ALLOC)", bytes);
+    hipError_t e = hipHostMalloc(&ar.stage[i], bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      ar.stage[i] = nullptr;
+      (void)hipGetLastError();
+      return fail(MS_ERR_NOMEM, "hipHostMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    ar.stage_bytes[i] = bytes;
+  }
+  *out = ar.stage[i];
+  *which = i;
+  return MS_OK;
+}
+
+int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<uint32_t>& idx,
+              uint64_t seed, hipStream_t st, unsigned long long* d_bits, DeviceCtx* dc) {
+  Arena* arp;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    arp = &dc->arenas[st];
+  }
+  std::lock_guard<std::mutex> alk(arp->mu);
+  Arena& ar = *arp;
+  const size_t head = offsetof(PlanArgs, lev);
+  const uint32_t wmax = wave_max_arrays();
+  size_t i0 = 0;
+  while (i0 < idx.size()) {
+    // the wave: arrays idx[i0 .. i1)
+    size_t i1 = i0, scratch = 0;
+    while (i1 < idx.size() && i1 - i0 < wmax) {
+      const HostPlan& hp = hps[i1];
+      const size_t need = align256(hp.lay.bytes) + align256(hp.n * hp.eb);
+      if (i1 > i0 && scratch + need > kWaveScratch) break;
+      scratch += need;
+      ++i1;
+    }
+    const uint32_t nw = (uint32_t)(i1 - i0);
+    // launch classes: leaves per element size; fused pass g per (g, size, levels)
+    auto cls_of = [](uint32_t eb) { return eb == 4 ? 0u : eb == 8 ? 1u : 2u; };
+    uint32_t nleaf[3] = {0, 0, 0};
+    std::map<uint32_t, uint32_t> gcount;  // key (g * 3 + cls) * 4 + lam - 1, ordered by pass
+    for (size_t i = i0; i < i1; ++i) {
+      const HostPlan& hp = hps[i];
+      const uint32_t cls = cls_of(hp.eb);
+      ++nleaf[cls];
+      for (uint32_t g = 0; g < hp.ngroup; ++g) ++gcount[(g * 3 + cls) * 4 + hp.glam[g] - 1];
+    }
+    size_t o = 0;
+    const size_t pa_off = o;
+    o += align256((size_t)nw * sizeof(PlanArgs));
+    size_t leaf_off[3], wpre_off[3];
+    for (int c = 0; c < 3; ++c) {
+      leaf_off[c] = o;
+      o += align256((size_t)nleaf[c] * sizeof(LeafArgs));
+      wpre_off[c] = o;
+      o += align256(((size_t)nleaf[c] + 1) * 4);
+    }
+    struct GSec {
+      size_t off, tpre_off;
+      uint32_t n, fill;
+    };
+    std::map<uint32_t, GSec> gsec;
+    for (const auto& kv : gcount) {
+      GSec sc;
+      sc.off = o;
+      o += align256((size_t)kv.second * sizeof(GroupArgs));
+      sc.tpre_off = o;
+      o += align256(((size_t)kv.second + 1) * 4);
+      sc.n = kv.second;
+      sc.fill = 0;
+      gsec[kv.first] = sc;
+    }
+    const size_t desc_bytes = o;
+    std::vector<size_t> plan_off(nw), data_off(nw);
+    for (uint32_t j = 0; j < nw; ++j) {
+      plan_off[j] = o;
+      o += align256(hps[i0 + j].lay.bytes);
+    }
+    for (uint32_t j = 0; j < nw; ++j) {
+      data_off[j] = o;
+      o += align256(hps[i0 + j].n * hps[i0 + j].eb);
+    }
+    int rc;
+    if ((rc = ensure(&ar.wave, &ar.wave_bytes, o, st))) return rc;
+    void* stg = nullptr;
+    int si = 0;
+    if ((rc = stage_buffer(ar, desc_bytes, &stg, &si))) return rc;
+    char* h = reinterpret_cast<char*>(stg);
+    char* d = reinterpret_cast<char*>(ar.wave);
+    uint32_t lfill[3] = {0, 0, 0}, lwg[3] = {0, 0, 0};
+    std::map<uint32_t, uint32_t> gtiles;
+    for (uint32_t j = 0; j < nw; ++j) {
+      HostPlan& hp = hps[i0 + j];
+      const uint32_t a = idx[i0 + j];
+      const uint64_t sa = seed + a;
+      unsigned long long* bits = d_bits ? d_bits + a : dc->dummy_bits;
+      PlanArgs& pa = hp.pa;
+      bind_plan(hp, d + plan_off[j]);
+      pa.key0 = (uint32_t)sa;
+      pa.key1 = (uint32_t)(sa >> 32);
+      pa.bits = bits;
+      pa.status = dc->status;
+      // only the levels and passes in use are read on the device
+      char* dst = h + pa_off + (size_t)j * sizeof(PlanArgs);
+      memcpy(dst, &pa, head);
+      memcpy(dst + head, pa.lev, hp.nlev * sizeof(HbmLevel));
+      memcpy(dst + offsetof(PlanArgs, grp), pa.grp, hp.ngroup * sizeof(GroupInfo));
+      void* X = ptrs[a];
+      void* Y = d + data_off[j];
+      void* cur = (hp.ngroup % 2 == 0) ? X : Y;
+      const uint32_t cls = cls_of(hp.eb);
+      LeafArgs la;
+      la.in = X;
+      la.out = cur;
+      la.n = hp.n;
+      la.c = hp.c;
+      la.lds_levels = hp.lam;
+      la.key0 = pa.key0;
+      la.key1 = pa.key1;
+      la.bits = bits;
+      memcpy(h + leaf_off[cls] + (size_t)lfill[cls] * sizeof(LeafArgs), &la, sizeof la);
+      reinterpret_cast<uint32_t*>(h + wpre_off[cls])[lfill[cls]] = lwg[cls];
+      ++lfill[cls];
+      lwg[cls] += (uint32_t)(hp.q >> hp.lam);
+      for (uint32_t g = 0; g < hp.ngroup; ++g) {
+        void* other = cur == X ? Y : X;
+        const GroupArgs ga = group_args(hp, g, cur, other);
+        const uint32_t key = (g * 3 + cls) * 4 + hp.glam[g] - 1;
+        GSec& sc = gsec[key];
+        memcpy(h + sc.off + (size_t)sc.fill * sizeof(GroupArgs), &ga, sizeof ga);
+        uint32_t& t = gtiles[key];
+        reinterpret_cast<uint32_t*>(h + sc.tpre_off)[sc.fill] = t;
+        t += ga.ntiles;
+        ++sc.fill;
+        cur = other;
+      }
+    }
+    for (int c = 0; c < 3; ++c) reinterpret_cast<uint32_t*>(h + wpre_off[c])[nleaf[c]] = lwg[c];
+    for (auto& kv : gsec) reinterpret_cast<uint32_t*>(h + kv.second.tpre_off)[kv.second.n] = gtiles[kv.first];
+    HIP_TRY(hipMemcpyAsync(d, h, desc_bytes, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(ar.stage_done[si], st));
+    {
+      ProfScope ps(0, st);
+      launch_plan_batch(reinterpret_cast<const PlanArgs*>(d + pa_off), nw, st);
+    }
+    for (int c = 0; c < 3; ++c) {
+      ProfScope ps(1, st);
+      launch_leaf_multi(reinterpret_cast<const LeafArgs*>(d + leaf_off[c]),
+                        reinterpret_cast<const uint32_t*>(d + wpre_off[c]), nleaf[c], lwg[c],
+                        c == 0 ? 4u : c == 1 ? 8u : 16u, st);
+    }
+    for (auto& kv : gsec) {
+      const uint32_t key = kv.first;
+      const uint32_t lam = key % 4 + 1, cls = (key / 4) % 3;
+      ProfScope ps(2, st);
+      launch_group_multi(reinterpret_cast<const GroupArgs*>(d + kv.second.off),
+                         reinterpret_cast<const uint32_t*>(d + kv.second.tpre_off), kv.second.n, gtiles[key],
+                         (int)lam, cls == 0 ? 4u : cls == 1 ? 8u : 16u, st);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MS_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
+    i0 = i1;
+  }
+  return MS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -485,19 +710,20 @@ int ms_shuffle_batched_ex(void* const* ptrs, const uint64_t* sizes, const uint32
   if (count == 0) return MS_OK;
   if (!ptrs || !sizes) return fail(MS_ERR_INVALID, "null pointer or size array");
   const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  std::vector<uint32_t> large;
+  // every argument is checked before anything is launched
+  for (uint32_t a = 0; a < count; ++a) {
+    const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
+    HostPlan hp;
+    int rc = make_plan(sizes[a], eb, cfg, hp);
+    if (rc) return rc;
+    if (sizes[a] > 0 && !ptrs[a]) return fail(MS_ERR_INVALID, "array %u: null pointer", a);
+    if (((uintptr_t)ptrs[a]) % eb != 0) return fail(MS_ERR_INVALID, "array %u: pointer not aligned to %u bytes", a, eb);
+  }
+  std::vector<uint32_t> wave_idx, large;
+  std::vector<HostPlan> wave_hp;
+  DeviceCtx* dc;
   {
-    // every argument is checked before anything is launched
-    for (uint32_t a = 0; a < count; ++a) {
-      const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
-      HostPlan hp;
-      int rc = make_plan(sizes[a], eb, cfg, hp);
-      if (rc) return rc;
-      if (sizes[a] > 0 && !ptrs[a]) return fail(MS_ERR_INVALID, "array %u: null pointer", a);
-      if (((uintptr_t)ptrs[a]) % eb != 0) return fail(MS_ERR_INVALID, "array %u: pointer not aligned to %u bytes", a, eb);
-    }
     std::lock_guard<std::mutex> lk(g_mu);
-    DeviceCtx* dc;
     int rc;
     if ((rc = device_ctx(&dc))) return rc;
     // arrays whose every merge level fits in one leaf workgroup: one
@@ -510,14 +736,19 @@ int ms_shuffle_batched_ex(void* const* ptrs, const uint64_t* sizes, const uint32
       launch_leaf_batch(jb[cls], nj[cls], cls == 0 ? 4u : cls == 1 ? 8u : 16u, st);
       nj[cls] = 0;
     };
+    HostPlan hp;
     for (uint32_t a = 0; a < count; ++a) {
       const uint64_t n = sizes[a];
       if (n <= 1) continue;
       const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
-      HostPlan hp;
       make_plan(n, eb, cfg, hp);
       if (hp.nlev) {
-        large.push_back(a);
+        if (wave_eligible(hp)) {
+          wave_idx.push_back(a);
+          wave_hp.push_back(hp);
+        } else {
+          large.push_back(a);
+        }
         continue;
       }
       const int cls = eb == 4 ? 0 : eb == 8 ? 1 : 2;
@@ -535,7 +766,14 @@ int ms_shuffle_batched_ex(void* const* ptrs, const uint64_t* sizes, const uint32
     }
     for (int cls = 0; cls < 3; ++cls) flush(cls);
     HIP_TRY(hipGetLastError());
-    if (large.size() > 1 && !dc->side_init) {
+  }
+  // the largest arrays take the full path each, spread over the side
+  // streams (forked from and joined back into the caller's stream) so that
+  // they overlap one another and the waves
+  const bool side = large.size() > 1 || (!large.empty() && !wave_idx.empty());
+  if (side) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!dc->side_init) {
       for (int i = 0; i < kSideStreams; ++i) {
         HIP_TRY(hipStreamCreateWithFlags(&dc->side[i], hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&dc->join[i], hipEventDisableTiming));
@@ -543,28 +781,19 @@ int ms_shuffle_batched_ex(void* const* ptrs, const uint64_t* sizes, const uint32
       HIP_TRY(hipEventCreateWithFlags(&dc->fork, hipEventDisableTiming));
       dc->side_init = true;
     }
-    if (large.size() > 1) {
-      HIP_TRY(hipEventRecord(dc->fork, st));
-      for (int i = 0; i < kSideStreams; ++i) HIP_TRY(hipStreamWaitEvent(dc->side[i], dc->fork, 0));
-    }
-  }
-  // arrays that need HBM passes: the full path each, spread over the side
-  // streams so that their small launches overlap
-  if (large.empty()) return MS_OK;
-  DeviceCtx* dc;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    int rc;
-    if ((rc = device_ctx(&dc))) return rc;
+    HIP_TRY(hipEventRecord(dc->fork, st));
+    for (int i = 0; i < kSideStreams; ++i) HIP_TRY(hipStreamWaitEvent(dc->side[i], dc->fork, 0));
   }
   int err = MS_OK;
   for (size_t i = 0; i < large.size() && err == MS_OK; ++i) {
     const uint32_t a = large[i];
     const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
-    const hipStream_t s2 = large.size() > 1 ? dc->side[i % kSideStreams] : st;
+    const hipStream_t s2 = side ? dc->side[i % kSideStreams] : st;
     err = run_one(ptrs[a], sizes[a], eb, seed + a, s2, cfg, d_bits_per_array ? d_bits_per_array + a : nullptr, false);
   }
-  if (large.size() > 1) {
+  if (err == MS_OK && !wave_idx.empty())
+    err = run_waves(ptrs, wave_hp, wave_idx, seed, st, d_bits_per_array, dc);
+  if (side) {
     // joined even after an error, so that the caller's stream still orders
     // after whatever was launched
     const std::string msg = g_err;

@@ -777,6 +777,21 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) le
   leaf_body<E, SCAP, NT, false>(jb.job[blockIdx.x], 0);
 }
 
+// The leaf kernels of many arrays in one launch: job j owns workgroups
+// [wpre[j], wpre[j+1]) of the nwg = wpre[njobs] workgroups.
+template <typename E, int SCAP, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+leaf_multi_kernel(const LeafArgs* __restrict__ jobs, const uint32_t* __restrict__ wpre, uint32_t njobs) {
+  const uint32_t w = blockIdx.x;
+  uint32_t lo = 0, hi = njobs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (wpre[mid] <= w) lo = mid;
+    else hi = mid;
+  }
+  leaf_body<E, SCAP, NT, false>(jobs[lo], w - wpre[lo]);
+}
+
 template <typename E, int SCAP, int NT, bool IDENT>
 static void launch_leaf_t(const LeafArgs& a, uint64_t grid, hipStream_t st) {
   hipLaunchKernelGGL((leaf_kernel<E, SCAP, NT, IDENT>), dim3((uint32_t)grid), dim3(NT), 0, st, a);
@@ -812,6 +827,23 @@ void launch_leaf_batch(const LeafBatch& jb, uint32_t njobs, uint32_t eb, hipStre
   } else {
     if (sm) hipLaunchKernelGGL((leaf_batch_kernel<uint4, 4096, 512>), g, dim3(512), 0, st, jb);
     else hipLaunchKernelGGL((leaf_batch_kernel<uint4, 8192, 1024>), g, dim3(1024), 0, st, jb);
+  }
+}
+
+void launch_leaf_multi(const LeafArgs* jobs, const uint32_t* wpre, uint32_t njobs, uint32_t nwg, uint32_t eb,
+                       hipStream_t st) {
+  if (!nwg) return;
+  const bool sm = leaf_small();
+  const dim3 g(nwg);
+  if (eb == 4) {
+    if (sm) hipLaunchKernelGGL((leaf_multi_kernel<uint32_t, 16384, 512>), g, dim3(512), 0, st, jobs, wpre, njobs);
+    else hipLaunchKernelGGL((leaf_multi_kernel<uint32_t, 32768, 1024>), g, dim3(1024), 0, st, jobs, wpre, njobs);
+  } else if (eb == 8) {
+    if (sm) hipLaunchKernelGGL((leaf_multi_kernel<uint64_t, 8192, 512>), g, dim3(512), 0, st, jobs, wpre, njobs);
+    else hipLaunchKernelGGL((leaf_multi_kernel<uint64_t, 16384, 1024>), g, dim3(1024), 0, st, jobs, wpre, njobs);
+  } else {
+    if (sm) hipLaunchKernelGGL((leaf_multi_kernel<uint4, 4096, 512>), g, dim3(512), 0, st, jobs, wpre, njobs);
+    else hipLaunchKernelGGL((leaf_multi_kernel<uint4, 8192, 1024>), g, dim3(1024), 0, st, jobs, wpre, njobs);
   }
 }
 

@@ -27,8 +27,9 @@ struct Win {
   uint64_t s;
 };
 
+// One tile of one fused pass (tile = top merge * tpm + tile within it).
 template <typename E, int T, int LAM, int NT>
-__global__ void __launch_bounds__(NT) group_kernel(GroupArgs a) {
+__device__ __forceinline__ void group_body(const GroupArgs& a, uint32_t tile) {
   constexpr int NODES = (1 << LAM) - 1;
   constexpr int NB = NODES / 2 + 1;  // bottom windows
   // flip words of every window: at most T/32 + 8 per window and level
@@ -61,16 +62,6 @@ __global__ void __launch_bounds__(NT) group_kernel(GroupArgs a) {
   const E* X = reinterpret_cast<const E*>(a.X);
   const R* XR = reinterpret_cast<const R*>(a.X);
   E* Z = reinterpret_cast<E*>(a.Z);
-  if (blockIdx.x >= a.ntiles) return;
-  // Workgroups are dealt to the 8 XCDs round robin; give each XCD a
-  // contiguous eighth of the tiles so that the tiles of one merge share an
-  // L2, which then also serves most insertion-loop fetches within the merge.
-  uint32_t tile;
-  {
-    const uint32_t q = a.ntiles >> 3, r = a.ntiles & 7u;
-    const uint32_t x = blockIdx.x & 7u, i = blockIdx.x >> 3;
-    tile = x * q + min(x, r) + i;
-  }
   const uint32_t M = tile / a.tpm;
   const uint32_t b = tile - M * a.tpm;
 
@@ -429,6 +420,38 @@ __global__ void __launch_bounds__(NT) group_kernel(GroupArgs a) {
   }
 }
 
+// Workgroups are dealt to the 8 XCDs round robin; give each XCD a
+// contiguous eighth of the tiles so that the tiles of one merge share an L2,
+// which then also serves most insertion-loop fetches within the merge.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t ntiles) {
+  const uint32_t q = ntiles >> 3, r = ntiles & 7u;
+  const uint32_t x = blockIdx.x & 7u, i = blockIdx.x >> 3;
+  return x * q + min(x, r) + i;
+}
+
+template <typename E, int T, int LAM, int NT>
+__global__ void __launch_bounds__(NT) group_kernel(GroupArgs a) {
+  if (blockIdx.x >= a.ntiles) return;
+  group_body<E, T, LAM, NT>(a, xcd_tile(a.ntiles));
+}
+
+// The same pass of many arrays in one launch: job j owns tiles
+// [tpre[j], tpre[j+1]) of the ntiles = tpre[njobs] tiles.
+template <typename E, int T, int LAM, int NT>
+__global__ void __launch_bounds__(NT) group_multi_kernel(const GroupArgs* __restrict__ jobs,
+                                                         const uint32_t* __restrict__ tpre, uint32_t njobs,
+                                                         uint32_t ntiles) {
+  if (blockIdx.x >= ntiles) return;
+  const uint32_t tile = xcd_tile(ntiles);
+  uint32_t lo = 0, hi = njobs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (tpre[mid] <= tile) lo = mid;
+    else hi = mid;
+  }
+  group_body<E, T, LAM, NT>(jobs[lo], tile - tpre[lo]);
+}
+
 // Slots per tile for 4-byte elements: 2048 with 256 threads (the default:
 // measured faster) or 4096 with 512 threads (MS_GROUP_TILE=4096).  A tuning
 // knob only: the permutation does not depend on it.
@@ -449,6 +472,29 @@ static void launch_group_t(const GroupArgs& a, int lam, uint64_t tiles, hipStrea
   else if (lam == 2) hipLaunchKernelGGL((group_kernel<E, T, 2, NT>), g, b, 0, st, a);
   else if (lam == 3) hipLaunchKernelGGL((group_kernel<E, T, 3, NT>), g, b, 0, st, a);
   else hipLaunchKernelGGL((group_kernel<E, T, 4, NT>), g, b, 0, st, a);
+}
+
+template <typename E, int T, int NT>
+static void launch_group_multi_t(const GroupArgs* jobs, const uint32_t* tpre, uint32_t njobs, uint32_t ntiles,
+                                 int lam, hipStream_t st) {
+  const dim3 g(ntiles), b(NT);
+  if (lam == 1) hipLaunchKernelGGL((group_multi_kernel<E, T, 1, NT>), g, b, 0, st, jobs, tpre, njobs, ntiles);
+  else if (lam == 2) hipLaunchKernelGGL((group_multi_kernel<E, T, 2, NT>), g, b, 0, st, jobs, tpre, njobs, ntiles);
+  else if (lam == 3) hipLaunchKernelGGL((group_multi_kernel<E, T, 3, NT>), g, b, 0, st, jobs, tpre, njobs, ntiles);
+  else hipLaunchKernelGGL((group_multi_kernel<E, T, 4, NT>), g, b, 0, st, jobs, tpre, njobs, ntiles);
+}
+
+void launch_group_multi(const GroupArgs* jobs, const uint32_t* tpre, uint32_t njobs, uint32_t ntiles, int lam,
+                        uint32_t eb, hipStream_t st) {
+  if (!ntiles) return;
+  if (eb == 4) {
+    if (group_tile_u32() == 2048) launch_group_multi_t<uint32_t, 2048, 256>(jobs, tpre, njobs, ntiles, lam, st);
+    else launch_group_multi_t<uint32_t, 4096, 512>(jobs, tpre, njobs, ntiles, lam, st);
+  } else if (eb == 8) {
+    launch_group_multi_t<uint64_t, 2048, 256>(jobs, tpre, njobs, ntiles, lam, st);
+  } else {
+    launch_group_multi_t<uint4, 1024, 256>(jobs, tpre, njobs, ntiles, lam, st);
+  }
 }
 
 void launch_group(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st) {

@@ -66,9 +66,7 @@ __device__ __forceinline__ MergeGeom merge_geom(const PlanArgs& pa, uint32_t L, 
 // ---------------------------------------------------------------------------
 // 1. zeros per granule and per chunk
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) plan_count_kernel(PlanArgs pa) {
-  __shared__ uint32_t tmp[8];
-  const uint64_t chunk = blockIdx.x;
+__device__ __forceinline__ void plan_count_body(const PlanArgs& pa, uint64_t chunk, uint32_t* tmp) {
   const int l = level_of_chunk(pa, chunk);
   const HbmLevel& lv = pa.lev[l];
   const uint64_t rel = chunk - lv.chunk_base;
@@ -82,6 +80,10 @@ __global__ void __launch_bounds__(256) plan_count_kernel(PlanArgs pa) {
   const uint32_t ex = block_excl_scan<256>(z, tmp, &total);
   pa.zloc[(chunk << kChunkGranLog) + threadIdx.x] = (uint16_t)ex;
   if (threadIdx.x == 0) pa.ctot[chunk] = total;
+}
+__global__ void __launch_bounds__(256) plan_count_kernel(PlanArgs pa) {
+  __shared__ uint32_t tmp[8];
+  plan_count_body(pa, blockIdx.x, tmp);
 }
 
 // Position (0..127) of the r-th zero (want_one = 0) or one (want_one = 1) of a block.
@@ -119,8 +121,7 @@ __device__ __forceinline__ uint32_t locate_in_chunk(const PlanArgs& pa, uint64_t
 // zc of every chunk from the global prefix of chunk zero counts (sums wrap
 // modulo 2^32, but every merge's own prefix stays below 2^32)
 // (and clears the bucket counters for the insertion-loop kernels)
-__global__ void __launch_bounds__(256) zc_kernel(PlanArgs pa) {
-  const uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void zc_body(const PlanArgs& pa, uint64_t c) {
   if (c < pa.total_buckets) {
     pa.bcnt[c] = 0;
     pa.bfill[c] = 0;
@@ -130,13 +131,12 @@ __global__ void __launch_bounds__(256) zc_kernel(PlanArgs pa) {
   const uint64_t first = c - (c - lv.chunk_base) % lv.cpm;
   pa.zc[c] = pa.zg[c] - pa.zg[first];
 }
+__global__ void __launch_bounds__(256) zc_kernel(PlanArgs pa) { zc_body(pa, (uint64_t)blockIdx.x * 256 + threadIdx.x); }
 
 // Per merge (one thread each): the chunk holding the (n1+1)-th zero and the
 // one holding the (n2+1)-th one by binary search over the chunk prefixes,
 // the flip inside it, and so the break step P and the side that ran out.
-__global__ void __launch_bounds__(256) plan_break_kernel(PlanArgs pa) {
-  __shared__ uint64_t red[4];
-  const uint64_t gm = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ uint64_t break_body(const PlanArgs& pa, uint64_t gm) {
   uint64_t used = 0;
   if (gm < pa.total_merges) {
     const int l = level_of_merge(pa, gm);
@@ -172,6 +172,11 @@ __global__ void __launch_bounds__(256) plan_break_kernel(PlanArgs pa) {
     pa.kcnt[gm] = g.N - P;
     used = (uint64_t)P + 1;
   }
+  return used;
+}
+__global__ void __launch_bounds__(256) plan_break_kernel(PlanArgs pa) {
+  __shared__ uint64_t red[4];
+  const uint64_t used = break_body(pa, (uint64_t)blockIdx.x * 256 + threadIdx.x);
   const uint64_t t = block_sum_u64<256>(used, red);
   if (threadIdx.x == 0 && t) atomicAdd(pa.bits, (unsigned long long)t);
 }
@@ -213,9 +218,8 @@ __device__ __forceinline__ TailWg tail_wg(const PlanArgs& pa, uint64_t wg) {
 // ---------------------------------------------------------------------------
 // 3. insertion-loop draws: count target entries per bucket (and the bits)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) tail_count_kernel(PlanArgs pa) {
-  __shared__ uint64_t red[4];
-  const TailWg t = tail_wg(pa, blockIdx.x);
+__device__ __forceinline__ void tail_count_body(const PlanArgs& pa, uint64_t wg, uint64_t* red) {
+  const TailWg t = tail_wg(pa, wg);
   uint32_t bits = 0;
   for (uint32_t d = t.w * 256 + threadIdx.x; d < t.k; d += t.lv->wpm * 256) {
     const uint32_t i = t.P + d;
@@ -224,6 +228,10 @@ __global__ void __launch_bounds__(256) tail_count_kernel(PlanArgs pa) {
   }
   const uint64_t s = block_sum_u64<256>(bits, red);
   if (threadIdx.x == 0 && s) atomicAdd(pa.bits, (unsigned long long)s);
+}
+__global__ void __launch_bounds__(256) tail_count_kernel(PlanArgs pa) {
+  __shared__ uint64_t red[4];
+  tail_count_body(pa, blockIdx.x, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -287,13 +295,13 @@ __global__ void __launch_bounds__(256) scan_down_kernel(const uint32_t* __restri
 
 // The same scan by one workgroup, for short arrays (one launch instead of three).
 constexpr uint64_t kScanOneMax = 65536;
-__global__ void __launch_bounds__(1024) scan_one_kernel(const uint32_t* __restrict__ in, uint64_t count,
-                                                        uint32_t* __restrict__ out, uint64_t cap, uint32_t* status,
-                                                        uint32_t flag) {
-  __shared__ uint32_t tmp[20];
+template <int NT>
+__device__ __forceinline__ void block_scan_all(const uint32_t* __restrict__ in, uint64_t count,
+                                               uint32_t* __restrict__ out, uint64_t cap, uint32_t* status,
+                                               uint32_t flag, uint32_t* tmp) {
   constexpr int K = 8;
   uint32_t running = 0;
-  for (uint64_t b0 = 0; b0 < count; b0 += 1024 * K) {
+  for (uint64_t b0 = 0; b0 < count; b0 += NT * K) {
     const uint64_t base = b0 + (uint64_t)threadIdx.x * K;
     uint32_t v[K];
     uint32_t sum = 0;
@@ -303,7 +311,7 @@ __global__ void __launch_bounds__(1024) scan_one_kernel(const uint32_t* __restri
       sum += v[k];
     }
     uint32_t tot;
-    uint32_t run = running + block_excl_scan<1024>(sum, tmp, &tot);
+    uint32_t run = running + block_excl_scan<NT>(sum, tmp, &tot);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (base + k < count) out[base + k] = run;
@@ -315,6 +323,12 @@ __global__ void __launch_bounds__(1024) scan_one_kernel(const uint32_t* __restri
     out[count] = running;
     if ((uint64_t)running > cap) atomicOr(status, flag);
   }
+}
+__global__ void __launch_bounds__(1024) scan_one_kernel(const uint32_t* __restrict__ in, uint64_t count,
+                                                        uint32_t* __restrict__ out, uint64_t cap, uint32_t* status,
+                                                        uint32_t flag) {
+  __shared__ uint32_t tmp[20];
+  block_scan_all<1024>(in, count, out, cap, status, flag, tmp);
 }
 
 static void launch_scan(const uint32_t* in, uint64_t count, uint32_t* part, uint32_t* out, uint64_t cap,
@@ -332,8 +346,8 @@ static void launch_scan(const uint32_t* in, uint64_t count, uint32_t* part, uint
 // ---------------------------------------------------------------------------
 // 5. insertion-loop draws again: scatter the target entries into buckets
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) tail_scatter_kernel(PlanArgs pa) {
-  const TailWg t = tail_wg(pa, blockIdx.x);
+__device__ __forceinline__ void tail_scatter_body(const PlanArgs& pa, uint64_t wg) {
+  const TailWg t = tail_wg(pa, wg);
   uint32_t bits = 0;
   for (uint32_t d = t.w * 256 + threadIdx.x; d < t.k; d += t.lv->wpm * 256) {
     const uint32_t i = t.P + d;
@@ -347,6 +361,7 @@ __global__ void __launch_bounds__(256) tail_scatter_kernel(PlanArgs pa) {
     }
   }
 }
+__global__ void __launch_bounds__(256) tail_scatter_kernel(PlanArgs pa) { tail_scatter_body(pa, blockIdx.x); }
 
 // Largest step s' < below among the steps that target slot y (y's own step excluded).
 __device__ __forceinline__ uint32_t max_target(const PlanArgs& pa, uint64_t bb, uint32_t blog, uint32_t y,
@@ -383,8 +398,8 @@ __device__ __forceinline__ uint32_t c0_offset(const PlanArgs& pa, const HbmLevel
 // ---------------------------------------------------------------------------
 // 6. resolve every touched slot: where its final value comes from
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) tail_resolve_kernel(PlanArgs pa) {
-  const TailWg t = tail_wg(pa, blockIdx.x);
+__device__ __forceinline__ void tail_resolve_body(const PlanArgs& pa, uint64_t wg) {
+  const TailWg t = tail_wg(pa, wg);
   const HbmLevel& lv = *t.lv;
   const uint32_t side = pa.side[t.gm];
   const uint64_t toff = pa.toff[t.gm];
@@ -425,6 +440,7 @@ __global__ void __launch_bounds__(256) tail_resolve_kernel(PlanArgs pa) {
     pa.pool_src[e] = out;
   }
 }
+__global__ void __launch_bounds__(256) tail_resolve_kernel(PlanArgs pa) { tail_resolve_body(pa, blockIdx.x); }
 
 // ---------------------------------------------------------------------------
 // 7. trace every resolved source down to the input of its fused pass
@@ -550,6 +566,45 @@ __device__ __forceinline__ void bounds_body(const PlanArgs& pa, uint64_t idx) {
 __global__ void __launch_bounds__(256) trace_bounds_kernel(PlanArgs pa) {
   if (blockIdx.x < pa.total_tail_wgs) trace_body(pa, blockIdx.x);
   else bounds_body(pa, (blockIdx.x - pa.total_tail_wgs) * 256 + threadIdx.x);
+}
+
+// The whole plan of one array per workgroup, for batches of arrays with few
+// HBM levels (the stages of launch_plan in order, a barrier between stages).
+__global__ void __launch_bounds__(256) plan_batch_kernel(const PlanArgs* __restrict__ pas) {
+  __shared__ uint32_t tmp[8];
+  __shared__ uint64_t red[4];
+  const PlanArgs& pa = pas[blockIdx.x];
+  if (pa.nlev == 0) return;
+  for (uint64_t c = 0; c < pa.total_chunks; ++c) plan_count_body(pa, c, tmp);
+  __syncthreads();
+  block_scan_all<256>(pa.ctot, pa.total_chunks, pa.zg, ~0ull, pa.status, 0u, tmp);
+  __syncthreads();
+  const uint64_t nz = pa.total_chunks > pa.total_buckets ? pa.total_chunks : pa.total_buckets;
+  for (uint64_t c = threadIdx.x; c < nz; c += 256) zc_body(pa, c);
+  __syncthreads();
+  uint64_t used = 0;
+  for (uint64_t gm = threadIdx.x; gm < pa.total_merges; gm += 256) used += break_body(pa, gm);
+  const uint64_t t = block_sum_u64<256>(used, red);
+  if (threadIdx.x == 0 && t) atomicAdd(pa.bits, (unsigned long long)t);
+  __syncthreads();
+  block_scan_all<256>(pa.kcnt, pa.total_merges, pa.toff, pa.tail_cap, pa.status, 2u, tmp);
+  __syncthreads();
+  for (uint64_t w = 0; w < pa.total_tail_wgs; ++w) tail_count_body(pa, w, red);
+  __syncthreads();
+  block_scan_all<256>(pa.bcnt, pa.total_buckets, pa.boff, pa.pool_cap, pa.status, 1u, tmp);
+  __syncthreads();
+  for (uint64_t w = 0; w < pa.total_tail_wgs; ++w) tail_scatter_body(pa, w);
+  __syncthreads();
+  for (uint64_t w = 0; w < pa.total_tail_wgs; ++w) tail_resolve_body(pa, w);
+  __syncthreads();
+  if (pa.tail_xsrc) {
+    for (uint64_t w = 0; w < pa.total_tail_wgs; ++w) trace_body(pa, w);
+    for (uint64_t i = threadIdx.x; i < pa.total_bnd; i += 256) bounds_body(pa, i);
+  }
+}
+
+void launch_plan_batch(const PlanArgs* d_pas, uint32_t count, hipStream_t st) {
+  if (count) hipLaunchKernelGGL(plan_batch_kernel, dim3(count), dim3(256), 0, st, d_pas);
 }
 
 void launch_plan(const PlanArgs& pa, hipStream_t st) {

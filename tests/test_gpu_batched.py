@@ -101,3 +101,21 @@ def test_batched_equals_one_call_per_array(M):
     torch.cuda.synchronize()
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+
+
+def test_arrays_in_several_waves(M, monkeypatch):
+    # arrays with HBM passes run in waves; three arrays per wave here
+    monkeypatch.setenv("MS_WAVE_ARRAYS", "3")
+    sizes = [16385, 40000, 3, 100000, 65536, 131073, 5000, 20000, 300001, 16384 * 3]
+    ebs = [4, 8, 4, 16, 4, 8, 4, 16, 4, 8]
+    _say("[gpu] batched waves of 3")
+    _check(M, sizes, ebs, 606)
+
+
+def test_full_path_arrays_beside_waves(M):
+    # arrays above the wave limit (2^21 elements) take the full path on the
+    # side streams while the others run in a wave
+    sizes = [(1 << 21) + 5, 40000, 1 << 21, 70001, (1 << 21) + 4096 * 3, 9000]
+    ebs = [4, 4, 8, 16, 4, 4]
+    _say("[gpu] batched full path + wave")
+    _check(M, sizes, ebs, 4242)
