@@ -26,13 +26,13 @@ namespace ms {
 void launch_group(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st);
 int group_tile(uint32_t eb);
 void launch_plan(const PlanArgs& pa, hipStream_t st);
-void launch_plan_batch(const PlanArgs* d_pas, uint32_t count, hipStream_t st);
+void launch_plan_multi(const PlanArgs* pas, uint32_t njobs, const uint32_t* const* pre, const uint32_t* units,
+                       hipStream_t st);
 void launch_leaf_multi(const LeafArgs* jobs, const uint32_t* wpre, uint32_t njobs, uint32_t nwg, uint32_t eb,
                        hipStream_t st);
 void launch_group_multi(const GroupArgs* jobs, const uint32_t* tpre, uint32_t njobs, uint32_t ntiles, int lam,
                         uint32_t eb, hipStream_t st);
 void launch_leaf(const LeafArgs& a, uint32_t eb, bool ident, uint64_t grid, hipStream_t st);
-void launch_leaf_batch(const LeafBatch& jb, uint32_t njobs, uint32_t eb, hipStream_t st);
 void launch_merge_pass(const PassArgs& a, uint32_t eb, uint64_t grid, hipStream_t st);
 void launch_patch(const PlanArgs& pa, int l, const void* in, void* out, uint32_t eb, hipStream_t st);
 int leaf_capacity(uint32_t eb);
@@ -484,15 +484,15 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
   return MS_OK;
 }
 
-// Arrays of a batch that need HBM passes but hold at most kWaveMaxN
-// elements run in waves: one plan launch for the whole wave (a workgroup per
-// array), one leaf launch per element size and one launch per (fused pass,
-// element size, levels in the pass), so that the launch count does not grow
-// with the number of arrays.  Every array gets its own plan tables and array
-// copy inside the wave's scratch.
+// The arrays of a batched call with at most kWaveMaxN elements run in
+// waves: per wave, one launch per plan stage for all of its arrays that need
+// HBM passes, one leaf launch per element size and one launch per (fused
+// pass, element size, levels in the pass), so that the launch count does not
+// grow with the number of arrays.  Every array has its own plan tables and
+// array copy inside the wave's scratch.
 constexpr uint64_t kWaveMaxN = 1ull << 21;
-constexpr size_t kWaveScratch = 512ull << 20;
-constexpr uint32_t kWaveMaxArrays = 4096;
+constexpr size_t kWaveScratch = 4ull << 30;
+constexpr uint32_t kWaveMaxArrays = 8192;
 
 // Arrays per wave: kWaveMaxArrays, or fewer through MS_WAVE_ARRAYS (a tuning
 // and testing knob; the permutations do not depend on it).
@@ -502,7 +502,7 @@ uint32_t wave_max_arrays() {
   return v > 0 && v < (long)kWaveMaxArrays ? (uint32_t)v : kWaveMaxArrays;
 }
 
-bool wave_eligible(const HostPlan& hp) { return hp.nlev > 0 && hp.fused && hp.n <= kWaveMaxN; }
+bool wave_eligible(const HostPlan& hp) { return hp.n <= kWaveMaxN && (hp.nlev == 0 || hp.fused); }
 
 int stage_buffer(Arena& ar, size_t bytes, void** out, int* which) {
   const int i = ar.stage_next;
@@ -528,8 +528,8 @@ int stage_buffer(Arena& ar, size_t bytes, void** out, int* which) {
   return MS_OK;
 }
 
-int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<uint32_t>& idx,
-              uint64_t seed, hipStream_t st, unsigned long long* d_bits, DeviceCtx* dc) {
+int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<uint32_t>& idx, uint64_t seed,
+              hipStream_t st, unsigned long long* d_bits, DeviceCtx* dc) {
   Arena* arp;
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -539,31 +539,39 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
   Arena& ar = *arp;
   const size_t head = offsetof(PlanArgs, lev);
   const uint32_t wmax = wave_max_arrays();
+  auto cls_of = [](uint32_t eb) { return eb == 4 ? 0u : eb == 8 ? 1u : 2u; };
   size_t i0 = 0;
   while (i0 < idx.size()) {
     // the wave: arrays idx[i0 .. i1)
     size_t i1 = i0, scratch = 0;
     while (i1 < idx.size() && i1 - i0 < wmax) {
       const HostPlan& hp = hps[i1];
-      const size_t need = align256(hp.lay.bytes) + align256(hp.n * hp.eb);
+      const size_t need = hp.nlev ? align256(hp.lay.bytes) + align256(hp.n * hp.eb) : 0;
       if (i1 > i0 && scratch + need > kWaveScratch) break;
       scratch += need;
       ++i1;
     }
     const uint32_t nw = (uint32_t)(i1 - i0);
-    // launch classes: leaves per element size; fused pass g per (g, size, levels)
-    auto cls_of = [](uint32_t eb) { return eb == 4 ? 0u : eb == 8 ? 1u : 2u; };
-    uint32_t nleaf[3] = {0, 0, 0};
+    // launch classes: plan jobs (arrays with HBM passes), leaves per element
+    // size, fused pass g per (g, element size, levels)
+    uint32_t np = 0, nleaf[3] = {0, 0, 0};
     std::map<uint32_t, uint32_t> gcount;  // key (g * 3 + cls) * 4 + lam - 1, ordered by pass
     for (size_t i = i0; i < i1; ++i) {
       const HostPlan& hp = hps[i];
       const uint32_t cls = cls_of(hp.eb);
       ++nleaf[cls];
+      if (hp.nlev) ++np;
       for (uint32_t g = 0; g < hp.ngroup; ++g) ++gcount[(g * 3 + cls) * 4 + hp.glam[g] - 1];
     }
     size_t o = 0;
     const size_t pa_off = o;
-    o += align256((size_t)nw * sizeof(PlanArgs));
+    o += align256((size_t)np * sizeof(PlanArgs));
+    constexpr int kUnits = 5;
+    size_t pre_off[kUnits];
+    for (int k = 0; k < kUnits; ++k) {
+      pre_off[k] = o;
+      o += align256(((size_t)np + 1) * 4);
+    }
     size_t leaf_off[3], wpre_off[3];
     for (int c = 0; c < 3; ++c) {
       leaf_off[c] = o;
@@ -573,7 +581,7 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
     }
     struct GSec {
       size_t off, tpre_off;
-      uint32_t n, fill;
+      uint32_t n, fill, tiles;
     };
     std::map<uint32_t, GSec> gsec;
     for (const auto& kv : gcount) {
@@ -584,15 +592,18 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
       o += align256(((size_t)kv.second + 1) * 4);
       sc.n = kv.second;
       sc.fill = 0;
+      sc.tiles = 0;
       gsec[kv.first] = sc;
     }
     const size_t desc_bytes = o;
-    std::vector<size_t> plan_off(nw), data_off(nw);
+    std::vector<size_t> plan_off(nw, 0), data_off(nw, 0);
     for (uint32_t j = 0; j < nw; ++j) {
+      if (!hps[i0 + j].nlev) continue;
       plan_off[j] = o;
       o += align256(hps[i0 + j].lay.bytes);
     }
     for (uint32_t j = 0; j < nw; ++j) {
+      if (!hps[i0 + j].nlev) continue;
       data_off[j] = o;
       o += align256(hps[i0 + j].n * hps[i0 + j].eb);
     }
@@ -603,28 +614,38 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
     if ((rc = stage_buffer(ar, desc_bytes, &stg, &si))) return rc;
     char* h = reinterpret_cast<char*>(stg);
     char* d = reinterpret_cast<char*>(ar.wave);
+    uint32_t pfill = 0, units[kUnits] = {0, 0, 0, 0, 0};
     uint32_t lfill[3] = {0, 0, 0}, lwg[3] = {0, 0, 0};
-    std::map<uint32_t, uint32_t> gtiles;
     for (uint32_t j = 0; j < nw; ++j) {
       HostPlan& hp = hps[i0 + j];
       const uint32_t a = idx[i0 + j];
       const uint64_t sa = seed + a;
       unsigned long long* bits = d_bits ? d_bits + a : dc->dummy_bits;
+      void* X = ptrs[a];
+      void* Y = hp.nlev ? d + data_off[j] : X;
+      void* cur = (hp.ngroup % 2 == 0) ? X : Y;
+      const uint32_t cls = cls_of(hp.eb);
       PlanArgs& pa = hp.pa;
-      bind_plan(hp, d + plan_off[j]);
       pa.key0 = (uint32_t)sa;
       pa.key1 = (uint32_t)(sa >> 32);
       pa.bits = bits;
       pa.status = dc->status;
-      // only the levels and passes in use are read on the device
-      char* dst = h + pa_off + (size_t)j * sizeof(PlanArgs);
-      memcpy(dst, &pa, head);
-      memcpy(dst + head, pa.lev, hp.nlev * sizeof(HbmLevel));
-      memcpy(dst + offsetof(PlanArgs, grp), pa.grp, hp.ngroup * sizeof(GroupInfo));
-      void* X = ptrs[a];
-      void* Y = d + data_off[j];
-      void* cur = (hp.ngroup % 2 == 0) ? X : Y;
-      const uint32_t cls = cls_of(hp.eb);
+      if (hp.nlev) {
+        bind_plan(hp, d + plan_off[j]);
+        // only the levels and passes in use are read on the device
+        char* dst = h + pa_off + (size_t)pfill * sizeof(PlanArgs);
+        memcpy(dst, &pa, head);
+        memcpy(dst + head, pa.lev, hp.nlev * sizeof(HbmLevel));
+        memcpy(dst + offsetof(PlanArgs, grp), pa.grp, hp.ngroup * sizeof(GroupInfo));
+        const uint64_t per[kUnits] = {pa.total_chunks, (std::max(pa.total_chunks, pa.total_buckets) + 255) / 256,
+                                      (pa.total_merges + 255) / 256, pa.total_tail_wgs,
+                                      pa.total_tail_wgs + (pa.total_bnd + 255) / 256};
+        for (int k = 0; k < kUnits; ++k) {
+          reinterpret_cast<uint32_t*>(h + pre_off[k])[pfill] = units[k];
+          units[k] += (uint32_t)per[k];
+        }
+        ++pfill;
+      }
       LeafArgs la;
       la.in = X;
       la.out = cur;
@@ -641,25 +662,27 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
       for (uint32_t g = 0; g < hp.ngroup; ++g) {
         void* other = cur == X ? Y : X;
         const GroupArgs ga = group_args(hp, g, cur, other);
-        const uint32_t key = (g * 3 + cls) * 4 + hp.glam[g] - 1;
-        GSec& sc = gsec[key];
+        GSec& sc = gsec[(g * 3 + cls) * 4 + hp.glam[g] - 1];
         memcpy(h + sc.off + (size_t)sc.fill * sizeof(GroupArgs), &ga, sizeof ga);
-        uint32_t& t = gtiles[key];
-        reinterpret_cast<uint32_t*>(h + sc.tpre_off)[sc.fill] = t;
-        t += ga.ntiles;
+        reinterpret_cast<uint32_t*>(h + sc.tpre_off)[sc.fill] = sc.tiles;
+        sc.tiles += ga.ntiles;
         ++sc.fill;
         cur = other;
       }
     }
+    for (int k = 0; k < kUnits; ++k) reinterpret_cast<uint32_t*>(h + pre_off[k])[np] = units[k];
     for (int c = 0; c < 3; ++c) reinterpret_cast<uint32_t*>(h + wpre_off[c])[nleaf[c]] = lwg[c];
-    for (auto& kv : gsec) reinterpret_cast<uint32_t*>(h + kv.second.tpre_off)[kv.second.n] = gtiles[kv.first];
+    for (auto& kv : gsec) reinterpret_cast<uint32_t*>(h + kv.second.tpre_off)[kv.second.n] = kv.second.tiles;
     HIP_TRY(hipMemcpyAsync(d, h, desc_bytes, hipMemcpyHostToDevice, st));
     HIP_TRY(hipEventRecord(ar.stage_done[si], st));
-    {
+    if (np) {
+      const uint32_t* pre[kUnits];
+      for (int k = 0; k < kUnits; ++k) pre[k] = reinterpret_cast<const uint32_t*>(d + pre_off[k]);
       ProfScope ps(0, st);
-      launch_plan_batch(reinterpret_cast<const PlanArgs*>(d + pa_off), nw, st);
+      launch_plan_multi(reinterpret_cast<const PlanArgs*>(d + pa_off), np, pre, units, st);
     }
     for (int c = 0; c < 3; ++c) {
+      if (!nleaf[c]) continue;
       ProfScope ps(1, st);
       launch_leaf_multi(reinterpret_cast<const LeafArgs*>(d + leaf_off[c]),
                         reinterpret_cast<const uint32_t*>(d + wpre_off[c]), nleaf[c], lwg[c],
@@ -670,7 +693,7 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
       const uint32_t lam = key % 4 + 1, cls = (key / 4) % 3;
       ProfScope ps(2, st);
       launch_group_multi(reinterpret_cast<const GroupArgs*>(d + kv.second.off),
-                         reinterpret_cast<const uint32_t*>(d + kv.second.tpre_off), kv.second.n, gtiles[key],
+                         reinterpret_cast<const uint32_t*>(d + kv.second.tpre_off), kv.second.n, kv.second.tiles,
                          (int)lam, cls == 0 ? 4u : cls == 1 ? 8u : 16u, st);
     }
     hipError_t e = hipGetLastError();
@@ -711,61 +734,32 @@ int ms_shuffle_batched_ex(void* const* ptrs, const uint64_t* sizes, const uint32
   if (!ptrs || !sizes) return fail(MS_ERR_INVALID, "null pointer or size array");
   const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   // every argument is checked before anything is launched
-  for (uint32_t a = 0; a < count; ++a) {
-    const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
-    HostPlan hp;
-    int rc = make_plan(sizes[a], eb, cfg, hp);
-    if (rc) return rc;
-    if (sizes[a] > 0 && !ptrs[a]) return fail(MS_ERR_INVALID, "array %u: null pointer", a);
-    if (((uintptr_t)ptrs[a]) % eb != 0) return fail(MS_ERR_INVALID, "array %u: pointer not aligned to %u bytes", a, eb);
-  }
   std::vector<uint32_t> wave_idx, large;
   std::vector<HostPlan> wave_hp;
+  wave_hp.reserve(count);
+  {
+    HostPlan hp;
+    for (uint32_t a = 0; a < count; ++a) {
+      const uint64_t n = sizes[a];
+      const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
+      int rc = make_plan(n, eb, cfg, hp);
+      if (rc) return fail(rc, "array %u: %s", a, g_err.c_str());
+      if (n > 0 && !ptrs[a]) return fail(MS_ERR_INVALID, "array %u: null pointer", a);
+      if (((uintptr_t)ptrs[a]) % eb != 0) return fail(MS_ERR_INVALID, "array %u: pointer not aligned to %u bytes", a, eb);
+      if (n <= 1) continue;
+      if (wave_eligible(hp)) {
+        wave_idx.push_back(a);
+        wave_hp.push_back(hp);
+      } else {
+        large.push_back(a);
+      }
+    }
+  }
   DeviceCtx* dc;
   {
     std::lock_guard<std::mutex> lk(g_mu);
     int rc;
     if ((rc = device_ctx(&dc))) return rc;
-    // arrays whose every merge level fits in one leaf workgroup: one
-    // workgroup each, kLeafBatch arrays per launch, per element size
-    LeafBatch jb[3];
-    uint32_t nj[3] = {0, 0, 0};
-    auto flush = [&](int cls) {
-      if (!nj[cls]) return;
-      ProfScope ps(1, st);
-      launch_leaf_batch(jb[cls], nj[cls], cls == 0 ? 4u : cls == 1 ? 8u : 16u, st);
-      nj[cls] = 0;
-    };
-    HostPlan hp;
-    for (uint32_t a = 0; a < count; ++a) {
-      const uint64_t n = sizes[a];
-      if (n <= 1) continue;
-      const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
-      make_plan(n, eb, cfg, hp);
-      if (hp.nlev) {
-        if (wave_eligible(hp)) {
-          wave_idx.push_back(a);
-          wave_hp.push_back(hp);
-        } else {
-          large.push_back(a);
-        }
-        continue;
-      }
-      const int cls = eb == 4 ? 0 : eb == 8 ? 1 : 2;
-      LeafArgs& la = jb[cls].job[nj[cls]++];
-      const uint64_t sa = seed + a;
-      la.in = ptrs[a];
-      la.out = ptrs[a];
-      la.n = n;
-      la.c = hp.c;
-      la.lds_levels = hp.lam;
-      la.key0 = (uint32_t)sa;
-      la.key1 = (uint32_t)(sa >> 32);
-      la.bits = d_bits_per_array ? d_bits_per_array + a : dc->dummy_bits;
-      if (nj[cls] == (uint32_t)kLeafBatch) flush(cls);
-    }
-    for (int cls = 0; cls < 3; ++cls) flush(cls);
-    HIP_TRY(hipGetLastError());
   }
   // the largest arrays take the full path each, spread over the side
   // streams (forked from and joined back into the caller's stream) so that

@@ -771,12 +771,6 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) le
   leaf_body<E, SCAP, NT, IDENT>(a, blockIdx.x);
 }
 
-// Whole small arrays, one per workgroup.
-template <typename E, int SCAP, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) leaf_batch_kernel(LeafBatch jb) {
-  leaf_body<E, SCAP, NT, false>(jb.job[blockIdx.x], 0);
-}
-
 // The leaf kernels of many arrays in one launch: job j owns workgroups
 // [wpre[j], wpre[j+1]) of the nwg = wpre[njobs] workgroups.
 template <typename E, int SCAP, int NT>
@@ -814,21 +808,6 @@ int leaf_capacity(uint32_t eb) {
 }
 int leaf_max_block() { return 4097; }
 int leaf_max_levels() { return 6; }
-
-void launch_leaf_batch(const LeafBatch& jb, uint32_t njobs, uint32_t eb, hipStream_t st) {
-  const bool sm = leaf_small();
-  const dim3 g(njobs);
-  if (eb == 4) {
-    if (sm) hipLaunchKernelGGL((leaf_batch_kernel<uint32_t, 16384, 512>), g, dim3(512), 0, st, jb);
-    else hipLaunchKernelGGL((leaf_batch_kernel<uint32_t, 32768, 1024>), g, dim3(1024), 0, st, jb);
-  } else if (eb == 8) {
-    if (sm) hipLaunchKernelGGL((leaf_batch_kernel<uint64_t, 8192, 512>), g, dim3(512), 0, st, jb);
-    else hipLaunchKernelGGL((leaf_batch_kernel<uint64_t, 16384, 1024>), g, dim3(1024), 0, st, jb);
-  } else {
-    if (sm) hipLaunchKernelGGL((leaf_batch_kernel<uint4, 4096, 512>), g, dim3(512), 0, st, jb);
-    else hipLaunchKernelGGL((leaf_batch_kernel<uint4, 8192, 1024>), g, dim3(1024), 0, st, jb);
-  }
-}
 
 void launch_leaf_multi(const LeafArgs* jobs, const uint32_t* wpre, uint32_t njobs, uint32_t nwg, uint32_t eb,
                        hipStream_t st) {

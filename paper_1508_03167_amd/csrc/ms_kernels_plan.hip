@@ -568,43 +568,76 @@ __global__ void __launch_bounds__(256) trace_bounds_kernel(PlanArgs pa) {
   else bounds_body(pa, (blockIdx.x - pa.total_tail_wgs) * 256 + threadIdx.x);
 }
 
-// The whole plan of one array per workgroup, for batches of arrays with few
-// HBM levels (the stages of launch_plan in order, a barrier between stages).
-__global__ void __launch_bounds__(256) plan_batch_kernel(const PlanArgs* __restrict__ pas) {
+// The plans of many arrays, one launch per stage of launch_plan: job j of a
+// stage owns workgroups [pre[j], pre[j+1]) (or workgroup j when the stage
+// takes one per array).
+enum PlanStage {
+  kStCount, kStScanZ, kStZc, kStBreak, kStScanK, kStTailCount, kStScanB, kStScatter, kStResolve, kStTrace, kStages
+};
+
+template <int S>
+__global__ void __launch_bounds__(256) plan_multi_kernel(const PlanArgs* __restrict__ pas,
+                                                         const uint32_t* __restrict__ pre, uint32_t njobs) {
   __shared__ uint32_t tmp[8];
   __shared__ uint64_t red[4];
-  const PlanArgs& pa = pas[blockIdx.x];
-  if (pa.nlev == 0) return;
-  for (uint64_t c = 0; c < pa.total_chunks; ++c) plan_count_body(pa, c, tmp);
-  __syncthreads();
-  block_scan_all<256>(pa.ctot, pa.total_chunks, pa.zg, ~0ull, pa.status, 0u, tmp);
-  __syncthreads();
-  const uint64_t nz = pa.total_chunks > pa.total_buckets ? pa.total_chunks : pa.total_buckets;
-  for (uint64_t c = threadIdx.x; c < nz; c += 256) zc_body(pa, c);
-  __syncthreads();
-  uint64_t used = 0;
-  for (uint64_t gm = threadIdx.x; gm < pa.total_merges; gm += 256) used += break_body(pa, gm);
-  const uint64_t t = block_sum_u64<256>(used, red);
-  if (threadIdx.x == 0 && t) atomicAdd(pa.bits, (unsigned long long)t);
-  __syncthreads();
-  block_scan_all<256>(pa.kcnt, pa.total_merges, pa.toff, pa.tail_cap, pa.status, 2u, tmp);
-  __syncthreads();
-  for (uint64_t w = 0; w < pa.total_tail_wgs; ++w) tail_count_body(pa, w, red);
-  __syncthreads();
-  block_scan_all<256>(pa.bcnt, pa.total_buckets, pa.boff, pa.pool_cap, pa.status, 1u, tmp);
-  __syncthreads();
-  for (uint64_t w = 0; w < pa.total_tail_wgs; ++w) tail_scatter_body(pa, w);
-  __syncthreads();
-  for (uint64_t w = 0; w < pa.total_tail_wgs; ++w) tail_resolve_body(pa, w);
-  __syncthreads();
-  if (pa.tail_xsrc) {
-    for (uint64_t w = 0; w < pa.total_tail_wgs; ++w) trace_body(pa, w);
-    for (uint64_t i = threadIdx.x; i < pa.total_bnd; i += 256) bounds_body(pa, i);
+  constexpr bool kPerArray = S == kStScanZ || S == kStScanK || S == kStScanB;
+  uint32_t j = blockIdx.x, u = 0;
+  if (!kPerArray) {
+    uint32_t lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (pre[mid] <= blockIdx.x) lo = mid;
+      else hi = mid;
+    }
+    j = lo;
+    u = blockIdx.x - pre[lo];
+  }
+  const PlanArgs& pa = pas[j];
+  if constexpr (S == kStCount) {
+    plan_count_body(pa, u, tmp);
+  } else if constexpr (S == kStScanZ) {
+    block_scan_all<256>(pa.ctot, pa.total_chunks, pa.zg, ~0ull, pa.status, 0u, tmp);
+  } else if constexpr (S == kStZc) {
+    zc_body(pa, (uint64_t)u * 256 + threadIdx.x);
+  } else if constexpr (S == kStBreak) {
+    const uint64_t t = block_sum_u64<256>(break_body(pa, (uint64_t)u * 256 + threadIdx.x), red);
+    if (threadIdx.x == 0 && t) atomicAdd(pa.bits, (unsigned long long)t);
+  } else if constexpr (S == kStScanK) {
+    block_scan_all<256>(pa.kcnt, pa.total_merges, pa.toff, pa.tail_cap, pa.status, 2u, tmp);
+  } else if constexpr (S == kStTailCount) {
+    tail_count_body(pa, u, red);
+  } else if constexpr (S == kStScanB) {
+    block_scan_all<256>(pa.bcnt, pa.total_buckets, pa.boff, pa.pool_cap, pa.status, 1u, tmp);
+  } else if constexpr (S == kStScatter) {
+    tail_scatter_body(pa, u);
+  } else if constexpr (S == kStResolve) {
+    tail_resolve_body(pa, u);
+  } else {
+    if (u < pa.total_tail_wgs) trace_body(pa, u);
+    else bounds_body(pa, (u - pa.total_tail_wgs) * 256 + threadIdx.x);
   }
 }
 
-void launch_plan_batch(const PlanArgs* d_pas, uint32_t count, hipStream_t st) {
-  if (count) hipLaunchKernelGGL(plan_batch_kernel, dim3(count), dim3(256), 0, st, d_pas);
+// pre[k]: per-job workgroup prefixes (njobs + 1 entries) and units[k] their
+// totals, for k = 0 chunks, 1 zc blocks, 2 break blocks, 3 insertion-loop
+// workgroups, 4 trace and boundary-record workgroups.
+void launch_plan_multi(const PlanArgs* pas, uint32_t njobs, const uint32_t* const* pre, const uint32_t* units,
+                       hipStream_t st) {
+  if (!njobs) return;
+  const dim3 b(256);
+  auto go = [&](auto kern, uint32_t grid, const uint32_t* p) {
+    if (grid) hipLaunchKernelGGL(kern, dim3(grid), b, 0, st, pas, p, njobs);
+  };
+  go(plan_multi_kernel<kStCount>, units[0], pre[0]);
+  go(plan_multi_kernel<kStScanZ>, njobs, nullptr);
+  go(plan_multi_kernel<kStZc>, units[1], pre[1]);
+  go(plan_multi_kernel<kStBreak>, units[2], pre[2]);
+  go(plan_multi_kernel<kStScanK>, njobs, nullptr);
+  go(plan_multi_kernel<kStTailCount>, units[3], pre[3]);
+  go(plan_multi_kernel<kStScanB>, njobs, nullptr);
+  go(plan_multi_kernel<kStScatter>, units[3], pre[3]);
+  go(plan_multi_kernel<kStResolve>, units[3], pre[3]);
+  go(plan_multi_kernel<kStTrace>, units[4], pre[4]);
 }
 
 void launch_plan(const PlanArgs& pa, hipStream_t st) {

@@ -108,13 +108,6 @@ struct LeafArgs {
   unsigned long long* bits;
 };
 
-// Up to kLeafBatch whole arrays that each fit in one leaf workgroup (every
-// merge level in LDS), one workgroup per array, passed by value.
-constexpr int kLeafBatch = 64;
-struct LeafBatch {
-  LeafArgs job[kLeafBatch];
-};
-
 struct PassArgs {
   const void* in;
   void* out;
