@@ -102,12 +102,16 @@ int ms_permutation(uint32_t* out, uint64_t n, uint64_t seed);
  * elements (host arrays of pointers and sizes), array a with seed + a: each
  * array ends exactly as ms_shuffle(ptrs[a], sizes[a], 4, seed + a) leaves it.
  * Arrays must not overlap.  Every argument is checked before anything is
- * launched (errors as for ms_shuffle, naming the array).  Arrays whose merge
- * levels all fit in one leaf workgroup (up to 16384 elements of 4 bytes, 8192
- * of 8, 4096 of 16) run 64 per launch, one workgroup each; larger arrays take
- * the full path on four library streams that wait for `stream` and that
- * `stream` waits for before its next work, so the call is ordered on `stream`
- * like any other.  Per-array scratch as for ms_shuffle, on those streams. */
+ * launched (errors as for ms_shuffle, naming the array).  Arrays of up to
+ * 2^21 elements run in waves on `stream`: per wave, one launch per plan stage,
+ * one leaf launch per element size and one launch per fused pass class, all
+ * arrays of the wave together (at most 8192 arrays and 4 GiB of scratch per
+ * wave: each array's plan tables and array copy; the descriptors pass through
+ * two pinned host buffers kept per stream, and the host waits before reusing
+ * one until the copy out of it has run).  Larger arrays take the full path on
+ * four library streams that wait for `stream` and that `stream` waits for
+ * before its next work, so the call is ordered on `stream` like any other;
+ * their scratch as for ms_shuffle, on those streams. */
 int ms_shuffle_batched(void* const* ptrs, const uint64_t* sizes, uint32_t count, uint64_t seed, void* stream);
 
 /* As above with explicit knobs and an optional device counter (+= bits). */
