@@ -97,19 +97,46 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
     }
   }
   {
+    // The first round of every draw at once (it takes the top bitlen(r)
+    // bits of the word and ends unless they exceed r); the draws it leaves
+    // open then run to the end one after the other per lane.
     constexpr uint32_t QN = 4 * BPT;
-    uint32_t qi = 0;
-    uint32_t r = 4 * lt, w = 0, v = 1, c = 0, used = 0, left = 32, kk = r + 1, bk = 0;
-    bool valid = r >= 1 && r < b;
-    if (valid) {
-      w = W[lb + r];
-      bk = 32 - __clz(r);
+    static_assert(QN <= 64, "open draws are tracked in a 64-bit mask");
+    uint64_t open = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < QN; ++q) {
+      const uint32_t r = 4 * (lt + tpl * (q >> 2)) + (q & 3u);
+      if (r >= 1 && r < b) {
+        const uint32_t bk = 32 - __clz(r);
+        const uint32_t x = W[lb + r] >> (32 - bk);
+        if (x <= r) {
+          W[lb + r] = x;
+          *bits += bk;
+        } else {
+          open |= 1ull << q;
+        }
+      }
     }
+    if (open) {
+      uint32_t r = 0, w = 0, v = 0, c = 0, used = 0, left = 0, kk = 0, bk = 0;
+      auto next = [&]() {
+        const uint32_t q = (uint32_t)__builtin_ctzll(open);
+        open &= open - 1;
+        r = 4 * (lt + tpl * (q >> 2)) + (q & 3u);
+        w = W[lb + r];
+        bk = 32 - __clz(r);
+        kk = r + 1;
+        // state after the rejected first round
+        v = (1u << bk) - kk;
+        c = (w >> (32 - bk)) - kk;
+        used = bk;
+        left = 32 - bk;
+      };
+      next();
 #pragma unroll 1
-    for (;;) {
-      bool done = true;
-      uint32_t res = 0;
-      if (valid) {
+      for (;;) {
+        bool done = true;
+        uint32_t res = 0;
         int jump = (int)bk - (32 - __clz(v));
         if ((v << jump) <= kk - 1) jump += 1;
         if (jump > (int)left) {
@@ -130,23 +157,11 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
             done = false;
           }
         }
-      }
-      if (done) {
-        if (valid) {
+        if (done) {
           W[lb + r] = res;
           *bits += used;
-        }
-        if (++qi == QN) break;
-        r = 4 * (lt + tpl * (qi >> 2)) + (qi & 3u);
-        valid = r >= 1 && r < b;
-        kk = r + 1;
-        v = 1;
-        c = 0;
-        used = 0;
-        left = 32;
-        if (valid) {
-          w = W[lb + r];
-          bk = 32 - __clz(r);
+          if (!open) break;
+          next();
         }
       }
     }
