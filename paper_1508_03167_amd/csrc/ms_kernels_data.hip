@@ -425,7 +425,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
   constexpr int KS = (SCAP + NT - 1) / NT;                     // slots per thread
   constexpr int BPT = (SCAP / 4 + kLeafMaxMerges + NT - 1) / NT;  // step blocks per thread
   static_assert(SCAP * sizeof(E) >= 4 * SCAP, "list heads and links live in the data region");
-  __shared__ E data[SCAP];
+  __shared__ __align__(16) E data[SCAP];
   __shared__ MergeAux<SCAP> maux;
   __shared__ uint32_t tmp[20];
   __shared__ uint32_t mP[kLeafMaxMerges];
@@ -543,47 +543,96 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
     uint32_t tv = (uint32_t)tid;
     asm volatile("" : "+v"(tv));
     const float inv_msize = (float)nm / (float)cnt;
-    uint32_t SRC[(KS + 1) / 2];
+    // slots go by groups of 4 consecutive slots (group q of this thread:
+    // slots 4 * (tid + q * NT) + j); a group inside one merge and before its
+    // break step shares one flip word pair: with o_j the ones among its
+    // first j flips, slot j takes B at n1 + t0 - r0 + o_j or A at r0 + j - o_j
+    constexpr int KG = (KS + 3) / 4;
+    uint32_t SRC[2 * KG];
 #pragma unroll
-    for (int k = 0; k < KS; ++k) {
-      const uint32_t s = tv + k * NT;
-      uint32_t src = 0;
-      if (s < cnt) {
+    for (int q = 0; q < KG; ++q) {
+      const uint32_t s0 = 4 * (tv + q * NT);
+      uint32_t src[4] = {0u, 0u, 0u, 0u};
+      if (s0 < cnt) {
         // merges of a level have sizes within one of each other
-        uint32_t mm = min((uint32_t)((float)s * inv_msize), nm - 1);
-        while (mm > 0 && mb[mm] > s) --mm;
-        while (mm + 1 < nm && mb[mm + 1] <= s) ++mm;
-        const uint32_t t = s - mb[mm];
-        const uint32_t n1 = mmid[mm] - mb[mm], n2 = mb[mm + 1] - mmid[mm];
-        const uint32_t P = mP[mm] >> 1, side = mP[mm] & 1;
-        if (t < P) {
-          const uint32_t w = mm * W + (t >> 5);
-          const uint32_t word = maux.words[w];
-          const uint32_t bp = t & 31;
-          const uint32_t r0 = maux.wpre[w] - maux.wpre[mm * W] + (uint32_t)__popc(~word & ((1u << bp) - 1u));
-          src = ((word >> bp) & 1u) ? n1 + (t - r0) : r0;
+        uint32_t mm = min((uint32_t)((float)s0 * inv_msize), nm - 1);
+        while (mm > 0 && mb[mm] > s0) --mm;
+        while (mm + 1 < nm && mb[mm + 1] <= s0) ++mm;
+        const uint32_t m0 = mb[mm], m1 = mb[mm + 1];
+        const uint32_t t0 = s0 - m0;
+        const uint32_t n1 = mmid[mm] - m0;
+        const uint32_t P = mP[mm] >> 1;
+        if (s0 + 4 <= m1 && t0 + 4 <= P) {
+          const uint32_t w = mm * W + (t0 >> 5);
+          const uint32_t wlo = maux.words[w], whi = maux.words[w + 1];
+          const uint32_t bp = t0 & 31;
+          const uint32_t r0 = maux.wpre[w] - maux.wpre[mm * W] + (uint32_t)__popc(~wlo & ((1u << bp) - 1u));
+          const uint32_t bits4 = (uint32_t)((((uint64_t)whi << 32) | wlo) >> bp);
+          const uint32_t ab = m0 + r0, bb = m0 + n1 + t0 - r0;
+          uint32_t o = 0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const uint32_t bit = (bits4 >> j) & 1u;
+            src[j] = bit ? bb + o : ab + j - o;
+            o += bit;
+          }
         } else {
-          src = side == 0 ? t : t - n2;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const uint32_t sj = s0 + j;
+            if (sj < cnt) {
+              uint32_t k = mm;
+              while (k + 1 < nm && mb[k + 1] <= sj) ++k;
+              const uint32_t t = sj - mb[k];
+              const uint32_t kn1 = mmid[k] - mb[k], kn2 = mb[k + 1] - mmid[k];
+              const uint32_t kP = mP[k] >> 1, side = mP[k] & 1;
+              uint32_t v;
+              if (t < kP) {
+                const uint32_t w = k * W + (t >> 5);
+                const uint32_t word = maux.words[w];
+                const uint32_t bp = t & 31;
+                const uint32_t r0 = maux.wpre[w] - maux.wpre[k * W] + (uint32_t)__popc(~word & ((1u << bp) - 1u));
+                v = ((word >> bp) & 1u) ? kn1 + (t - r0) : r0;
+              } else {
+                v = side == 0 ? t : t - kn2;
+              }
+              src[j] = v + mb[k];
+            }
+          }
         }
-        src += mb[mm];
       }
-      if (k & 1) SRC[k >> 1] |= src << 16;
-      else SRC[k >> 1] = src;
+      SRC[2 * q] = src[0] | (src[1] << 16);
+      SRC[2 * q + 1] = src[2] | (src[3] << 16);
     }
     using R = typename RegOf<E>::type;
     R* dataR = reinterpret_cast<R*>(data);
-    R val[KS];
+    R val[4 * KG];
 #pragma unroll
-    for (int k = 0; k < KS; ++k) {
-      const uint32_t s = tv + k * NT;
-      if (s < cnt) val[k] = dataR[get16(SRC[k >> 1], k & 1)];
+    for (int q = 0; q < KG; ++q) {
+      const uint32_t s0 = 4 * (tv + q * NT);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (s0 + j < cnt) val[4 * q + j] = dataR[get16(SRC[2 * q + (j >> 1)], j & 1)];
     }
     __syncthreads();
     asm volatile("" : "+v"(tv));
 #pragma unroll
-    for (int k = 0; k < KS; ++k) {
-      const uint32_t s = tv + k * NT;
-      if (s < cnt) dataR[s] = val[k];
+    for (int q = 0; q < KG; ++q) {
+      const uint32_t s0 = 4 * (tv + q * NT);
+      if constexpr (sizeof(E) == 4) {
+        if (s0 + 4 <= cnt) {
+          uint4 o4;
+          o4.x = *reinterpret_cast<const uint32_t*>(&val[4 * q]);
+          o4.y = *reinterpret_cast<const uint32_t*>(&val[4 * q + 1]);
+          o4.z = *reinterpret_cast<const uint32_t*>(&val[4 * q + 2]);
+          o4.w = *reinterpret_cast<const uint32_t*>(&val[4 * q + 3]);
+          *reinterpret_cast<uint4*>(&data[s0]) = o4;
+          continue;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (s0 + j < cnt) dataR[s0 + j] = val[4 * q + j];
     }
     __syncthreads();
     // insertion loops, one wave per merge; the flip words are dead now and
