@@ -238,7 +238,7 @@ def main():
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": traffic_from_profiles("merge_pass_n2^30_u32"),
-                "kernel": "group_kernel<uint32_t,2048,levels>", "avg_launch_ms": round(avg, 4),
+                "kernel": "group_kernel<uint32_t,4096,levels>", "avg_launch_ms": round(avg, 4),
                 "launches": cnt_cls["merge_pass"],
                 "levels_per_launch": round(plan["hbm_levels"] * args.steps / launches, 3),
                 "alg_bytes_per_launch": 2 * n * 4}

@@ -452,13 +452,13 @@ __global__ void __launch_bounds__(NT) group_multi_kernel(const GroupArgs* __rest
   group_body<E, T, LAM, NT>(jobs[lo], tile - tpre[lo]);
 }
 
-// Slots per tile for 4-byte elements: 2048 with 256 threads (the default:
-// measured faster) or 4096 with 512 threads (MS_GROUP_TILE=4096).  A tuning
+// Slots per tile for 4-byte elements: 4096 with 512 threads (the default:
+// measured faster) or 2048 with 256 threads (MS_GROUP_TILE=2048).  A tuning
 // knob only: the permutation does not depend on it.
 static int group_tile_u32() {
   static const int t = [] {
     const char* e = getenv("MS_GROUP_TILE");
-    return e && atoi(e) == 4096 ? 4096 : 2048;
+    return e && atoi(e) == 2048 ? 2048 : 4096;
   }();
   return t;
 }
