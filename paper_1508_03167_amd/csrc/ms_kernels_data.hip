@@ -279,41 +279,44 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
   // 4. top() of every slot by pointer jumping over the up() links (each
   //    round halves the remaining chain), then F[r] = top(nxt(r)) or j_r,
   //    F[0] = top(0)
+  //    A slot whose pointer is NONE or points at a chain end is final and
+  //    drops out of the later rounds.
+  static_assert(4 * BPT <= 64, "live slots are tracked in a 64-bit mask");
+  uint64_t live = ~0ull;
   for (;;) {
     uint32_t nt[BPT][2];
-    bool changed = false;
+    uint64_t upd = 0;
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
       const uint32_t g = lt + tpl * k;
       nt[k][0] = nt[k][1] = 0u;
-      if (4 * g < b) {
-        uint32_t v[4];
+      uint32_t v[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const uint32_t x = 4 * g + e;
-          v[e] = NONE;
-          if (x < b) {
-            const uint32_t t = head[lb + x];
-            if (t != NONE) {
-              const uint32_t tt = head[lb + t];
-              v[e] = tt != NONE ? tt : t;
-              changed |= tt != NONE;
-            }
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t x = 4 * g + e;
+        const uint64_t bit = 1ull << (4 * k + e);
+        if ((live & bit) && x < b) {
+          const uint32_t t = head[lb + x];
+          const uint32_t tt = t != NONE ? (uint32_t)head[lb + t] : NONE;
+          if (tt != NONE) {
+            v[e] = tt;
+            upd |= bit;
           }
         }
-        nt[k][0] = (v[0] & 0xFFFFu) | (v[1] << 16);
-        nt[k][1] = (v[2] & 0xFFFFu) | (v[3] << 16);
       }
+      nt[k][0] = (v[0] & 0xFFFFu) | (v[1] << 16);
+      nt[k][1] = (v[2] & 0xFFFFu) | (v[3] << 16);
     }
+    live = upd;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
       const uint32_t g = lt + tpl * k;
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (4 * g + e < b) head[lb + 4 * g + e] = (uint16_t)get16(nt[k][e >> 1], e & 1);
+        if (upd & (1ull << (4 * k + e))) head[lb + 4 * g + e] = (uint16_t)get16(nt[k][e >> 1], e & 1);
     }
-    if (!__syncthreads_or(changed)) break;
+    if (!__syncthreads_or(upd != 0)) break;
   }
   // head[x] is now the end of x's up() chain, or NONE if x has no up()
 #pragma unroll
