@@ -105,6 +105,32 @@ def bench_batched(M, torch, reps: int = 3, count: int = 4096, seed: int = 3):
             "speedup": round(tl / tb, 3)}
 
 
+def bench_r1(M, torch, n_log2: int = 26, seed: int = 7, reps: int = 5):
+    """The printed listing's in-place placement (every level a one-level HBM
+    pass whose A slots are gathered through the swap chains) against the
+    default path and the default placement run the same way, uint32 identity."""
+    n = 1 << n_log2
+    x = torch.empty(n, dtype=torch.int32, device="cuda:0")
+
+    def timed(**kw):
+        M.permutation(x, seed, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            M.permutation(x, seed, **kw)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t1 = timed(placement="R1")
+    t2 = timed(hbm_only=True, one_level_passes=True)
+    t0 = timed()
+    del x
+    return {"workload": f"MergeShuffle permutation of 0..2^{n_log2}-1, seed {seed}, cutoff 4096, "
+                        f"listing placement (R1)",
+            "n": n, "r1_ms": round(t1 * 1e3, 3), "r1_gelem_s": round(n / t1 / 1e9, 3),
+            "stable_one_level_hbm_only_ms": round(t2 * 1e3, 3), "default_path_ms": round(t0 * 1e3, 3)}
+
+
 def bench_served(M, torch, count: int = 400, seed: int = 5, load: float = 0.7):
     """Requests of log-uniform size in [2^10, 2^26] elements, uint32 or uint64,
     Poisson arrivals at `load` times the measured capacity; request r uses seed
@@ -189,7 +215,7 @@ def main():
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=29)
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched and served workloads")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched, served and listing-placement workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 2^28 uint32 (1 GiB) for counter calibration")
     args = ap.parse_args()
@@ -286,6 +312,8 @@ def main():
         out["batched"] = bench_batched(M, torch)
         torch.cuda.empty_cache()
         out["served"] = bench_served(M, torch)
+        torch.cuda.empty_cache()
+        out["r1_placement"] = bench_r1(M, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_log2)
     print(json.dumps(out), flush=True)

@@ -83,11 +83,21 @@ typedef struct ms_config {
   uint32_t flags;           /* MS_CFG_HBM_ONLY: run every merge level as an HBM pass;
                                MS_CFG_ONE_LEVEL_PASSES: one streaming pass plus one patch
                                kernel per HBM level instead of fused passes (levels_per_pass
-                               is then ignored) */
+                               is then ignored);
+                               MS_CFG_PLACEMENT_R1: place the elements of each merge's
+                               coin-flip loop as the printed Merge listing's in-place swaps do
+                               (Section 4 listing; the default places them by the stable
+                               interleave).  The same bits, break steps and draws are used and
+                               the same B elements land on the same slots; only the order of
+                               the A elements differs.  Every level then runs as a one-level
+                               HBM pass (implies the two flags above) and the A slots are
+                               gathered, so this mode is much slower; it exists to reproduce the
+                               listing exactly. */
 } ms_config;
 
 #define MS_CFG_HBM_ONLY 1u
 #define MS_CFG_ONE_LEVEL_PASSES 2u
+#define MS_CFG_PLACEMENT_R1 4u
 
 /* Shuffle n elements of elem_bytes bytes at dev_ptr in place (Algorithm
  * MergeShuffle with cutoff 4096), seed as above, on stream. */
@@ -145,7 +155,9 @@ uint64_t ms_scratch_bytes(uint64_t n, uint32_t elem_bytes);
 uint32_t ms_leaf_B_for(uint64_t n, uint32_t elem_bytes);
 
 /* Synchronize `stream`, then read and clear the device status flags of the
- * current device (bit 0: target pool overflow, bit 1: tail pool overflow).
+ * current device (bit 0: target pool overflow, bit 1: tail pool overflow,
+ * bit 2: a placement chain of MS_CFG_PLACEMENT_R1 did not descend; an internal
+ * error that a valid plan never raises).
  * Returns MS_OK if clear, MS_ERR_CAPACITY if a flag was set. */
 int ms_device_status(void* stream, uint32_t* flags);
 

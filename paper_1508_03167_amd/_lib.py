@@ -20,6 +20,7 @@ MS_ERR_HIP = -4
 MS_ERR_CAPACITY = -5
 MS_CFG_HBM_ONLY = 1
 MS_CFG_ONE_LEVEL_PASSES = 2
+MS_CFG_PLACEMENT_R1 = 4
 
 SYMBOLS = [
     "ms_shuffle", "ms_permutation", "ms_shuffle_batched", "ms_shuffle_ex", "ms_permutation_ex",
@@ -88,10 +89,14 @@ def _check(rc: int):
         raise MSError(rc, lib().ms_last_error().decode())
 
 
-def _cfg(leaf_B=0, lds_levels_max=0, hbm_only=False, levels_per_pass=0, one_level_passes=False):
-    if not (leaf_B or lds_levels_max or hbm_only or levels_per_pass or one_level_passes):
+def _cfg(leaf_B=0, lds_levels_max=0, hbm_only=False, levels_per_pass=0, one_level_passes=False, placement="R2"):
+    if placement not in ("R1", "R2"):
+        raise ValueError(f"placement {placement!r} is neither 'R1' nor 'R2'")
+    r1 = placement == "R1"
+    if not (leaf_B or lds_levels_max or hbm_only or levels_per_pass or one_level_passes or r1):
         return None
-    flags = (MS_CFG_HBM_ONLY if hbm_only else 0) | (MS_CFG_ONE_LEVEL_PASSES if one_level_passes else 0)
+    flags = ((MS_CFG_HBM_ONLY if hbm_only else 0) | (MS_CFG_ONE_LEVEL_PASSES if one_level_passes else 0)
+             | (MS_CFG_PLACEMENT_R1 if r1 else 0))
     return ctypes.byref(MSConfig(leaf_B, levels_per_pass, lds_levels_max, flags))
 
 
@@ -110,47 +115,50 @@ def _ptr(t):
 
 
 def shuffle_(t, seed: int, *, stream=None, bits=None, leaf_B=0, lds_levels_max=0, hbm_only=False,
-             levels_per_pass=0, one_level_passes=False):
+             levels_per_pass=0, one_level_passes=False, placement="R2"):
     """Shuffle the contiguous device tensor t in place along its first dimension
-    (row size 4, 8 or 16 bytes).  bits: optional int64 device tensor, += bits used."""
+    (row size 4, 8 or 16 bytes).  bits: optional int64 device tensor, += bits used.
+    placement "R1" places each merge's elements as the printed listing's swaps do."""
     assert t.is_cuda and t.is_contiguous()
     eb = t.element_size() * (t[0].numel() if t.dim() > 1 else 1)
     n = t.shape[0]
     rc = lib().ms_shuffle_ex(_ptr(t), n, eb, seed & (2**64 - 1), _stream(stream),
-                             _cfg(leaf_B, lds_levels_max, hbm_only, levels_per_pass, one_level_passes),
+                             _cfg(leaf_B, lds_levels_max, hbm_only, levels_per_pass, one_level_passes, placement),
                              ctypes.c_void_p(bits.data_ptr()) if bits is not None else None)
     _check(rc)
     return t
 
 
 def permutation(out, seed: int, *, stream=None, bits=None, leaf_B=0, lds_levels_max=0, hbm_only=False,
-                levels_per_pass=0, one_level_passes=False):
+                levels_per_pass=0, one_level_passes=False, placement="R2"):
     """Write MergeShuffle's permutation of 0..n-1 into the int32/uint32 device tensor out."""
     assert out.is_cuda and out.is_contiguous() and out.element_size() == 4
     rc = lib().ms_permutation_ex(_ptr(out), out.numel(), seed & (2**64 - 1), _stream(stream),
-                                 _cfg(leaf_B, lds_levels_max, hbm_only, levels_per_pass, one_level_passes),
+                                 _cfg(leaf_B, lds_levels_max, hbm_only, levels_per_pass, one_level_passes, placement),
                                  ctypes.c_void_p(bits.data_ptr()) if bits is not None else None)
     _check(rc)
     return out
 
 
-def shuffle_batched_(tensors, seed: int, *, stream=None, bits=None, leaf_B=0):
+def shuffle_batched_(tensors, seed: int, *, stream=None, bits=None, leaf_B=0, placement="R2"):
     """Shuffle each device tensor of the list in place; tensor a uses seed + a."""
     cnt = len(tensors)
     ptrs = (ctypes.c_void_p * max(cnt, 1))(*[t.data_ptr() for t in tensors])
     sizes = (ctypes.c_uint64 * max(cnt, 1))(*[t.shape[0] for t in tensors])
     ebs = (ctypes.c_uint32 * max(cnt, 1))(
         *[t.element_size() * (t[0].numel() if t.dim() > 1 else 1) for t in tensors])
-    rc = lib().ms_shuffle_batched_ex(ptrs, sizes, ebs, cnt, seed & (2**64 - 1), _stream(stream), _cfg(leaf_B),
+    rc = lib().ms_shuffle_batched_ex(ptrs, sizes, ebs, cnt, seed & (2**64 - 1), _stream(stream),
+                                     _cfg(leaf_B, placement=placement),
                                      ctypes.c_void_p(bits.data_ptr()) if bits is not None else None)
     _check(rc)
     return tensors
 
 
 def plan(n: int, elem_bytes: int = 4, leaf_B=0, lds_levels_max=0, hbm_only=False, levels_per_pass=0,
-         one_level_passes=False) -> dict:
+         one_level_passes=False, placement="R2") -> dict:
     info = MSPlanInfo()
-    _check(lib().ms_plan(n, elem_bytes, _cfg(leaf_B, lds_levels_max, hbm_only, levels_per_pass, one_level_passes),
+    _check(lib().ms_plan(n, elem_bytes, _cfg(leaf_B, lds_levels_max, hbm_only, levels_per_pass, one_level_passes,
+                                             placement),
                          ctypes.byref(info)))
     return {f: getattr(info, f) for f, _ in MSPlanInfo._fields_}
 

@@ -35,6 +35,7 @@ void launch_group_multi(const GroupArgs* jobs, const uint32_t* tpre, uint32_t nj
 void launch_leaf(const LeafArgs& a, uint32_t eb, bool ident, uint64_t grid, hipStream_t st);
 void launch_merge_pass(const PassArgs& a, uint32_t eb, uint64_t grid, hipStream_t st);
 void launch_patch(const PlanArgs& pa, int l, const void* in, void* out, uint32_t eb, hipStream_t st);
+void launch_merge_r1(const PlanArgs& pa, int l, const void* in, void* out, uint32_t eb, hipStream_t st);
 int leaf_capacity(uint32_t eb);
 int leaf_max_block();
 int leaf_max_levels();
@@ -111,7 +112,9 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
                                            (unsigned long long)ceil_shift(n, c));
   uint32_t lam_max = (uint32_t)leaf_max_levels();
   if (cfg && cfg->lds_levels_max && cfg->lds_levels_max < lam_max) lam_max = cfg->lds_levels_max;
+  const bool r1 = cfg && (cfg->flags & MS_CFG_PLACEMENT_R1);
   if (cfg && (cfg->flags & MS_CFG_HBM_ONLY)) lam_max = 0;  // every merge level as an HBM pass
+  if (r1) lam_max = 0;  // the leaf kernel's merge levels use the stable interleave
   uint32_t lam = 0;
   while (lam < c && lam < lam_max && ceil_shift(n, c - lam - 1) <= scap) ++lam;
   hp.lam = lam;
@@ -160,7 +163,8 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
   // sizes within one; or one streaming pass and one patch kernel per level
   uint32_t lpp = cfg && cfg->levels_per_pass ? cfg->levels_per_pass : 3u;
   if (lpp > (uint32_t)kGroupMax) lpp = kGroupMax;
-  hp.fused = !(cfg && (cfg->flags & MS_CFG_ONE_LEVEL_PASSES));
+  hp.fused = !(cfg && (cfg->flags & MS_CFG_ONE_LEVEL_PASSES)) && !r1;
+  pa.placement = r1 ? 1u : 0u;
   if (!hp.fused) lpp = 1;
   hp.ngroup = hp.nlev ? (hp.nlev + lpp - 1) / lpp : 0;
   {
@@ -471,7 +475,8 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
     a.vec_ok = ((uintptr_t)cur % 16 == 0) ? 1u : 0u;
     {
       ProfScope ps(2, st);
-      launch_merge_pass(a, eb, (uint64_t)lv.nmerge * lv.tpm, st);
+      if (pa.placement) launch_merge_r1(pa, (int)l, cur, other, eb, st);
+      else launch_merge_pass(a, eb, (uint64_t)lv.nmerge * lv.tpm, st);
     }
     {
       ProfScope ps(3, st);

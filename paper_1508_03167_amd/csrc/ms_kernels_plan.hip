@@ -379,10 +379,50 @@ __device__ __forceinline__ uint32_t max_target(const PlanArgs& pa, uint64_t bb, 
   return best;
 }
 
+// The printed Merge listing's placement (in-place swaps).  A one at step t
+// swaps slot t with slot n1 + (ones before t), the next B element; a zero
+// leaves slot t alone.  So a slot p >= n1, once its B element has left, holds
+// what slot t_{p-n1} held at that swap (t_r = step of the r-th one, r from
+// 0), and the element a zero at step t keeps, or that slot t >= P holds at
+// the break when B ran out, is A[f(t)]: f(q) = q for q < n1, else
+// f(t_{q-n1}), with t_{q-n1} < q.  Everything else (the B slots, the break,
+// the insertion loop) is the same as for the stable interleave.
+
+// Step of the r-th one flip (r from 0) of merge m of level lv.
+__device__ __forceinline__ uint32_t nth_one(const PlanArgs& pa, const HbmLevel& lv, uint32_t m, uint32_t r) {
+  const uint64_t cb = lv.chunk_base + (uint64_t)m * lv.cpm;
+  uint32_t lo = 0, hi = lv.cpm - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (((uint64_t)mid << kChunkLog) - pa.zc[cb + mid] <= r) lo = mid;
+    else hi = mid - 1;
+  }
+  const uint32_t o0 = (uint32_t)(((uint64_t)lo << kChunkLog) - pa.zc[cb + lo]);
+  return locate_in_chunk(pa, cb + lo, lo, m, lv.L, r - o0, 1);
+}
+
+// f(q) above.  Every step lowers q; a step that would not (only a broken
+// plan could give one) sets status bit 2 and ends the chain.
+__device__ __forceinline__ uint32_t r1_a_source(const PlanArgs& pa, const HbmLevel& lv, uint32_t m, uint32_t n1,
+                                                uint32_t q) {
+  while (q >= n1) {
+    const uint32_t nq = nth_one(pa, lv, m, q - n1);
+    if (nq >= q) {
+      atomicOr(pa.status, 4u);
+      return 0u;
+    }
+    q = nq;
+  }
+  return q;
+}
+
 // Merge-relative input offset of C0[src] (the array before the insertion loop).
 __device__ __forceinline__ uint32_t c0_offset(const PlanArgs& pa, const HbmLevel& lv, uint32_t m,
                                               const MergeGeom& g, uint32_t P, uint32_t side, uint32_t src) {
-  if (src >= P) return side == 0 ? src : src - g.n2;
+  if (src >= P) {
+    if (side == 0) return src;
+    return pa.placement ? r1_a_source(pa, lv, m, g.n1, src) : src - g.n2;
+  }
   const uint64_t cglob = lv.chunk_base + (uint64_t)m * lv.cpm + (src >> kChunkLog);
   const uint32_t gi = src >> kGranLog;
   const W4 f = flip_block(gi, m, lv.L, Key{pa.key0, pa.key1});
@@ -392,7 +432,8 @@ __device__ __forceinline__ uint32_t c0_offset(const PlanArgs& pa, const HbmLevel
   const uint32_t word = pick(f, wsel);
   const uint32_t bit = src & 31;
   z += (uint32_t)__popc(~word & ((1u << bit) - 1u));
-  return ((word >> bit) & 1u) ? g.n1 + (src - z) : z;
+  if ((word >> bit) & 1u) return g.n1 + (src - z);
+  return pa.placement ? r1_a_source(pa, lv, m, g.n1, src) : z;
 }
 
 // ---------------------------------------------------------------------------
@@ -556,6 +597,33 @@ __device__ __forceinline__ void bounds_body(const PlanArgs& pa, uint64_t idx) {
       rec[2 * k] = u[k];
       rec[2 * k + 1] = ra[k];
     }
+}
+
+// ---------------------------------------------------------------------------
+// 9. one merge level with the listing's placement: every slot gathers its
+//    value before the insertion loop (the patch kernel then applies the loop)
+// ---------------------------------------------------------------------------
+template <typename E>
+__global__ void __launch_bounds__(256) merge_r1_kernel(PlanArgs pa, int l, const void* vin, void* vout) {
+  const HbmLevel& lv = pa.lev[l];
+  const uint32_t bpm = (lv.nmax + 255) / 256;  // workgroups per merge
+  const uint32_t m = blockIdx.x / bpm;
+  const uint32_t t = (blockIdx.x % bpm) * 256 + threadIdx.x;
+  const MergeGeom g = merge_geom(pa, lv.L, m);
+  if (t >= g.N) return;
+  const uint64_t gm = lv.merge_base + m;
+  const uint32_t src = c0_offset(pa, lv, m, g, pa.P[gm], pa.side[gm], t);
+  const E* in = reinterpret_cast<const E*>(vin);
+  E* out = reinterpret_cast<E*>(vout);
+  out[g.s + t] = in[g.s + (src < g.N ? src : t)];
+}
+
+void launch_merge_r1(const PlanArgs& pa, int l, const void* in, void* out, uint32_t eb, hipStream_t st) {
+  const HbmLevel& lv = pa.lev[l];
+  const dim3 grid((uint32_t)((uint64_t)lv.nmerge * ((lv.nmax + 255) / 256)));
+  if (eb == 4) hipLaunchKernelGGL(merge_r1_kernel<uint32_t>, grid, dim3(256), 0, st, pa, l, in, out);
+  else if (eb == 8) hipLaunchKernelGGL(merge_r1_kernel<uint64_t>, grid, dim3(256), 0, st, pa, l, in, out);
+  else hipLaunchKernelGGL(merge_r1_kernel<uint4>, grid, dim3(256), 0, st, pa, l, in, out);
 }
 
 // ---------------------------------------------------------------------------

@@ -59,7 +59,7 @@ struct PlanArgs {
   uint32_t c;             // levels
   uint32_t lds_levels;    // levels run inside the leaf kernel
   uint32_t nlev;          // HBM levels: L = lds_levels+1 .. c
-  uint32_t pad0;
+  uint32_t placement;     // 0: stable interleave; 1: in-place swaps of the printed Merge listing
   uint32_t key0, key1;    // seed
   uint64_t total_chunks;
   uint64_t total_merges;

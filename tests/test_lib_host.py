@@ -76,3 +76,17 @@ def test_rejects_bad_arguments_without_a_device():
     assert L.ms_plan(10, 3, None, ctypes.byref(info)) == -2
     assert L.ms_scratch_bytes(1 << 20, 4) > 4 << 20
     assert L.ms_leaf_B_for(1 << 20, 4) == 4096
+
+
+def test_listing_placement_plans_every_level_as_one_level_pass():
+    # the listing's in-place placement (R1) runs every merge level as a
+    # one-level HBM pass: the leaf kernel's LDS merges use the stable interleave
+    M, _ = _lib()
+    for n in (1 << 20, (1 << 24) + 12345, 4097):
+        p2 = M.plan(n)
+        p1 = M.plan(n, placement="R1")
+        assert p1["levels"] == p2["levels"]
+        assert p1["lds_levels"] == 0
+        assert p1["hbm_levels"] == p1["levels"]
+    with pytest.raises(ValueError):
+        M.plan(1000, placement="R3")
