@@ -29,21 +29,23 @@
 
 namespace ms {
 
-__device__ __forceinline__ int level_of_chunk(const PlanArgs& pa, uint64_t idx) {
-  int l = (int)pa.nlev - 1;
-  while (l > 0 && pa.lev[l].chunk_base > idx) --l;
-  return l;
-}
-__device__ __forceinline__ int level_of_merge(const PlanArgs& pa, uint64_t idx) {
-  int l = (int)pa.nlev - 1;
-  while (l > 0 && pa.lev[l].merge_base > idx) --l;
-  return l;
-}
-__device__ __forceinline__ int level_of_wg(const PlanArgs& pa, uint64_t idx) {
-  int l = (int)pa.nlev - 1;
-  while (l > 0 && pa.lev[l].wg_base > idx) --l;
-  return l;
-}
+// The HBM level whose range of a per-level index (chunk, merge or tail
+// workgroup) holds idx: the last level whose first index is <= idx (binary
+// search: most indices belong to the lowest levels).
+#define MS_LEVEL_OF(name, field)                                         \
+  __device__ __forceinline__ int name(const PlanArgs& pa, uint64_t idx) { \
+    int lo = 0, hi = (int)pa.nlev - 1;                                    \
+    while (lo < hi) {                                                     \
+      const int mid = (lo + hi + 1) >> 1;                                 \
+      if (pa.lev[mid].field <= idx) lo = mid;                             \
+      else hi = mid - 1;                                                  \
+    }                                                                     \
+    return lo;                                                            \
+  }
+MS_LEVEL_OF(level_of_chunk, chunk_base)
+MS_LEVEL_OF(level_of_merge, merge_base)
+MS_LEVEL_OF(level_of_wg, wg_base)
+#undef MS_LEVEL_OF
 
 struct MergeGeom {
   uint64_t s;   // first element
