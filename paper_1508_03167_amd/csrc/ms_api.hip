@@ -72,7 +72,7 @@ constexpr uint32_t kDefaultB = 4096;
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t zloc, ctot, zc, zg, P, side, kcnt, toff, tail_src, bcnt, bfill, boff, part, pool_x, pool_step, pool_src,
-      tail_xsrc, pool_xsrc, bnd;
+      tail_xsrc, pool_xsrc, bnd, bits_part;
   size_t bytes;
 };
 
@@ -229,6 +229,7 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
   y.tail_xsrc = hp.fused ? take(cap * 4) : 0;
   y.pool_xsrc = hp.fused ? take(cap * 4) : 0;
   y.bnd = hp.fused ? take(all_bnd * kBndStride * 4) : 0;
+  y.bits_part = take(kBitsParts * 8);
   y.bytes = hp.nlev ? o : 0;
   return MS_OK;
 }
@@ -356,6 +357,7 @@ void bind_plan(HostPlan& hp, void* area) {
   pa.tail_xsrc = hp.fused ? reinterpret_cast<uint32_t*>(b + y.tail_xsrc) : nullptr;
   pa.pool_xsrc = hp.fused ? reinterpret_cast<uint32_t*>(b + y.pool_xsrc) : nullptr;
   pa.bnd = hp.fused ? reinterpret_cast<uint32_t*>(b + y.bnd) : nullptr;
+  pa.bits_part = reinterpret_cast<unsigned long long*>(b + y.bits_part);
 }
 
 // Arguments of fused pass g, reading cur and writing other.

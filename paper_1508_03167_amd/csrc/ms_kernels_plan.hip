@@ -124,6 +124,7 @@ __device__ __forceinline__ uint32_t locate_in_chunk(const PlanArgs& pa, uint64_t
 // modulo 2^32, but every merge's own prefix stays below 2^32)
 // (and clears the bucket counters for the insertion-loop kernels)
 __device__ __forceinline__ void zc_body(const PlanArgs& pa, uint64_t c) {
+  if (c < (uint64_t)kBitsParts) pa.bits_part[c] = 0;
   if (c < pa.total_buckets) {
     pa.bcnt[c] = 0;
     pa.bfill[c] = 0;
@@ -228,8 +229,10 @@ __device__ __forceinline__ void tail_count_body(const PlanArgs& pa, uint64_t wg,
     const uint32_t j = tail_draw(pa, t.lv->L, t.m, i, &bits);
     if (j != i) atomicAdd(&pa.bcnt[t.bb + (j >> t.lv->blog)], 1u);
   }
+  // one of kBitsParts partial counters: tens of thousands of workgroups
+  // adding to one address would serialize on it
   const uint64_t s = block_sum_u64<256>(bits, red);
-  if (threadIdx.x == 0 && s) atomicAdd(pa.bits, (unsigned long long)s);
+  if (threadIdx.x == 0 && s) atomicAdd(&pa.bits_part[wg % kBitsParts], (unsigned long long)s);
 }
 __global__ void __launch_bounds__(256) tail_count_kernel(PlanArgs pa) {
   __shared__ uint64_t red[4];
@@ -348,7 +351,13 @@ static void launch_scan(const uint32_t* in, uint64_t count, uint32_t* part, uint
 // ---------------------------------------------------------------------------
 // 5. insertion-loop draws again: scatter the target entries into buckets
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void tail_scatter_body(const PlanArgs& pa, uint64_t wg) {
+__device__ __forceinline__ void tail_scatter_body(const PlanArgs& pa, uint64_t wg, uint64_t* red) {
+  if (wg == 0) {
+    // the count kernel's partial bit counters, added once
+    static_assert(kBitsParts == 256, "one counter per thread");
+    const uint64_t s = block_sum_u64<256>(pa.bits_part[threadIdx.x], red);
+    if (threadIdx.x == 0 && s) atomicAdd(pa.bits, (unsigned long long)s);
+  }
   const TailWg t = tail_wg(pa, wg);
   uint32_t bits = 0;
   for (uint32_t d = t.w * 256 + threadIdx.x; d < t.k; d += t.lv->wpm * 256) {
@@ -363,7 +372,10 @@ __device__ __forceinline__ void tail_scatter_body(const PlanArgs& pa, uint64_t w
     }
   }
 }
-__global__ void __launch_bounds__(256) tail_scatter_kernel(PlanArgs pa) { tail_scatter_body(pa, blockIdx.x); }
+__global__ void __launch_bounds__(256) tail_scatter_kernel(PlanArgs pa) {
+  __shared__ uint64_t red[4];
+  tail_scatter_body(pa, blockIdx.x, red);
+}
 
 // Largest step s' < below among the steps that target slot y (y's own step excluded).
 __device__ __forceinline__ uint32_t max_target(const PlanArgs& pa, uint64_t bb, uint32_t blog, uint32_t y,
@@ -679,7 +691,7 @@ __global__ void __launch_bounds__(256) plan_multi_kernel(const PlanArgs* __restr
   } else if constexpr (S == kStScanB) {
     block_scan_all<256>(pa.bcnt, pa.total_buckets, pa.boff, pa.pool_cap, pa.status, 1u, tmp);
   } else if constexpr (S == kStScatter) {
-    tail_scatter_body(pa, u);
+    tail_scatter_body(pa, u, red);
   } else if constexpr (S == kStResolve) {
     tail_resolve_body(pa, u);
   } else {

@@ -18,6 +18,7 @@
 namespace ms {
 
 constexpr int kMaxLevels = 32;
+constexpr int kBitsParts = 256;        // partial bit counters of the insertion-loop count kernel
 constexpr int kGroupMax = 4;           // merge levels fused into one HBM pass, at most
 constexpr uint32_t kGranLog = 7;       // 128 flips per granule (one Philox block)
 constexpr uint32_t kChunkGranLog = 8;  // 256 granules per chunk
@@ -89,6 +90,7 @@ struct PlanArgs {
   uint32_t* bnd;          // boundary records of every fused pass
   uint64_t total_bnd;
   unsigned long long* bits;
+  unsigned long long* bits_part;  // kBitsParts partial sums of the insertion-loop draws' bits
   uint32_t* status;
   uint32_t ngroup;
   uint32_t pad1;
