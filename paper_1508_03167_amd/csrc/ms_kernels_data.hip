@@ -18,7 +18,7 @@
 // with up(x) = min{r' > x : j_r' = x} and top() following up() to its end:
 //   F[r] = T0[top(nxt(r))] if nxt(r) = min{r' > r : j_r' = j_r} exists,
 //          T0[j_r] otherwise;     F[0] = T0[top(0)].
-// The lists of steps per target slot are built with LDS atomics.
+// The lists of steps per target slot are built with LDS atomic exchanges.
 //
 // Insertion loop in LDS.  A merge's tail steps i = P..N-1 run as groups of
 // 64 steps on one wave: within a group each lane resolves its step against
@@ -68,9 +68,9 @@ __device__ __forceinline__ uint32_t xchg_u16(uint16_t* arr, uint32_t pos, uint32
 __device__ __forceinline__ uint32_t get16(uint32_t packed, int half) { return (packed >> (16 * half)) & 0xFFFFu; }
 
 // Fisher-Yates of every leaf of the super-block at once (Algorithm 1 per leaf).
-// Before the elements are loaded, the LDS data region holds, per super-block
-// slot, a 16-bit list head (steps targeting the slot, later up()) and a
-// 16-bit list link.  Each thread owns blocks of 4 consecutive steps of one
+// Before the elements are loaded, the LDS data region holds one 32-bit word
+// per super-block slot: a 16-bit list head (steps targeting the slot, later
+// up()) and a 16-bit list link (later nxt()).  Each thread owns blocks of 4 consecutive steps of one
 // leaf (the steps whose draws share one Philox block) and returns, packed two
 // per register, the leaf-relative source F of each of its slots.
 template <int BPT, int NT>
@@ -78,6 +78,9 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
                                                 uint32_t lt, uint32_t tpl, uint32_t cnt, Key key, uint32_t* bits,
                                                 uint32_t (&F)[BPT][2]) {
   constexpr uint32_t NONE = 0xFFFFu;
+  uint16_t* const half = head;  // the lists' words, as 16-bit halves
+#define HED(y) half[2 * (y)]
+#define LNK(y) half[2 * (y) + 1]
   uint32_t J[BPT][2];
   // 1. the draws j_r, r = 1..b-1, of this thread's blocks (r = 4g..4g+3,
   //    g = lt + tpl*k).  The primary words go to the data region first (one
@@ -179,45 +182,37 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
     J[k][1] = jj[2] | (jj[3] << 16);
   }
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < (cnt + 1) / 2; i += NT) reinterpret_cast<uint32_t*>(head)[i] = 0xFFFFFFFFu;
+  // Lists in LDS: one 32-bit word per super-block slot y, its low half the
+  // head of y's list (later up(y)), its high half the link of step y (later
+  // nxt(y)).  Pushing r onto the list of slot j_r is one atomic exchange of
+  // the word (low half r): lanes that push onto one slot at once each get
+  // the head left by the one before them, so no push is ever retried.  The
+  // links wait in registers until every push is done.
+  for (uint32_t i = threadIdx.x; i < cnt; i += NT) W[i] = 0xFFFFFFFFu;
   __syncthreads();
-  // push r onto the list of slot j_r: the four steps of a block go out
-  // together and only the rare lost races retry
+  {
+    uint32_t LK[BPT][2];
 #pragma unroll
-  for (int k = 0; k < BPT; ++k) {
-    const uint32_t g = lt + tpl * k;
-    if (4 * g < b) {
-      uint32_t jj[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) jj[e] = get16(J[k][e >> 1], e & 1);
-      uint32_t cur[4];
-      bool todo[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        todo[e] = jj[e] != NONE;
-        cur[e] = todo[e] ? reinterpret_cast<uint32_t*>(head)[(lb + jj[e]) >> 1] : 0u;
-      }
-      for (;;) {
-        bool any = false;
+    for (int k = 0; k < BPT; ++k) {
+      const uint32_t g = lt + tpl * k;
+      uint32_t lk[4] = {NONE, NONE, NONE, NONE};
+      if (4 * g < b) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          if (todo[e]) {
-            const uint32_t pos = lb + jj[e];
-            const uint32_t sh = (pos & 1u) * 16u;
-            const uint32_t r = 4 * g + e;
-            const uint32_t nv = (cur[e] & ~(0xFFFFu << sh)) | (r << sh);
-            const uint32_t prev = atomicCAS(reinterpret_cast<uint32_t*>(head) + (pos >> 1), cur[e], nv);
-            if (prev == cur[e]) {
-              link[lb + r] = (uint16_t)((prev >> sh) & 0xFFFFu);
-              todo[e] = false;
-            } else {
-              cur[e] = prev;
-              any = true;
-            }
-          }
+          const uint32_t jx = get16(J[k][e >> 1], e & 1);
+          if (jx != NONE) lk[e] = atomicExch(&W[lb + jx], 0xFFFF0000u | (4 * g + e)) & 0xFFFFu;
         }
-        if (!any) break;
       }
+      LK[k][0] = lk[0] | (lk[1] << 16);
+      LK[k][1] = lk[2] | (lk[3] << 16);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+      const uint32_t g = lt + tpl * k;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (4 * g + e < b) LNK(lb + 4 * g + e) = (uint16_t)get16(LK[k][e >> 1], e & 1);
     }
   }
   __syncthreads();
@@ -233,8 +228,8 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
       for (int e = 0; e < 4; ++e) {
         const uint32_t x = 4 * g + e;
         const uint32_t jx = get16(J[k][e >> 1], e & 1);
-        pu[e] = x < b ? (uint32_t)head[lb + x] : NONE;
-        px[e] = (x >= 1 && x < b) ? (uint32_t)head[lb + jx] : NONE;
+        pu[e] = x < b ? (uint32_t)HED(lb + x) : NONE;
+        px[e] = (x >= 1 && x < b) ? (uint32_t)HED(lb + jx) : NONE;
         bu[e] = NONE;
         bx[e] = NONE;
       }
@@ -247,12 +242,12 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
           if (pu[e] != NONE) {
             any = true;
             if (pu[e] > x && pu[e] < bu[e]) bu[e] = pu[e];
-            pu[e] = link[lb + pu[e]];
+            pu[e] = LNK(lb + pu[e]);
           }
           if (px[e] != NONE) {
             any = true;
             if (px[e] > x && px[e] < bx[e]) bx[e] = px[e];
-            px[e] = link[lb + px[e]];
+            px[e] = LNK(lb + px[e]);
           }
         }
         if (!any) break;
@@ -264,15 +259,15 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
     }
   }
   __syncthreads();
-  // 3. head[] now holds up(x) and link[] nxt(r)
+  // 3. the low halves now hold up(x) and the high halves nxt(r)
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
     const uint32_t g = lt + tpl * k;
 #pragma unroll
     for (int e = 0; e < 4; ++e)
       if (4 * g + e < b) {
-        head[lb + 4 * g + e] = (uint16_t)get16(U[k][e >> 1], e & 1);
-        link[lb + 4 * g + e] = (uint16_t)get16(X[k][e >> 1], e & 1);
+        HED(lb + 4 * g + e) = (uint16_t)get16(U[k][e >> 1], e & 1);
+        LNK(lb + 4 * g + e) = (uint16_t)get16(X[k][e >> 1], e & 1);
       }
   }
   __syncthreads();
@@ -296,8 +291,8 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
         const uint32_t x = 4 * g + e;
         const uint64_t bit = 1ull << (4 * k + e);
         if ((live & bit) && x < b) {
-          const uint32_t t = head[lb + x];
-          const uint32_t tt = t != NONE ? (uint32_t)head[lb + t] : NONE;
+          const uint32_t t = HED(lb + x);
+          const uint32_t tt = t != NONE ? (uint32_t)HED(lb + t) : NONE;
           if (tt != NONE) {
             v[e] = tt;
             upd |= bit;
@@ -314,11 +309,11 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
       const uint32_t g = lt + tpl * k;
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (upd & (1ull << (4 * k + e))) head[lb + 4 * g + e] = (uint16_t)get16(nt[k][e >> 1], e & 1);
+        if (upd & (1ull << (4 * k + e))) HED(lb + 4 * g + e) = (uint16_t)get16(nt[k][e >> 1], e & 1);
     }
     if (!__syncthreads_or(upd != 0)) break;
   }
-  // head[x] is now the end of x's up() chain, or NONE if x has no up()
+  // the low half of x's word is now the end of x's up() chain, or NONE if x has no up()
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
     const uint32_t g = lt + tpl * k;
@@ -328,11 +323,11 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const uint32_t x = 4 * g + e;
-        const uint32_t nx = x < b ? (uint32_t)link[lb + x] : NONE;
+        const uint32_t nx = x < b ? (uint32_t)LNK(lb + x) : NONE;
         const uint32_t t = x == 0 ? 0u : nx;
         f[e] = get16(J[k][e >> 1], e & 1);
         if (x < b && (x == 0 || nx != NONE)) {
-          const uint32_t top = head[lb + t];
+          const uint32_t top = HED(lb + t);
           f[e] = top != NONE ? top : t;
         }
       }
@@ -341,6 +336,8 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
     }
   }
   __syncthreads();
+#undef HED
+#undef LNK
 }
 
 // Insertion loop of one merge [s0, s0+N) in LDS by one wave, groups of 64
