@@ -156,8 +156,10 @@ uint32_t ms_leaf_B_for(uint64_t n, uint32_t elem_bytes);
 
 /* Synchronize `stream`, then read and clear the device status flags of the
  * current device (bit 0: target pool overflow, bit 1: tail pool overflow,
- * bit 2: a placement chain of MS_CFG_PLACEMENT_R1 did not descend; an internal
- * error that a valid plan never raises).
+ * bit 2: a placement chain of MS_CFG_PLACEMENT_R1 did not descend; bit 3: the
+ * leaf kernel found two same-slot list pushes out of step order, i.e. the
+ * device did not apply one wave's same-address LDS exchanges in lane order;
+ * bits 2 and 3 are internal errors that mean a wrong result).
  * Returns MS_OK if clear, MS_ERR_CAPACITY if a flag was set. */
 int ms_device_status(void* stream, uint32_t* flags);
 

@@ -441,6 +441,7 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
     la.key0 = pa.key0;
     la.key1 = pa.key1;
     la.bits = bits;
+    la.status = dc->status;
     ProfScope ps(1, st);
     launch_leaf(la, eb, ident, hp.q >> hp.lam, st);
   }
@@ -662,6 +663,7 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
       la.key0 = pa.key0;
       la.key1 = pa.key1;
       la.bits = bits;
+      la.status = dc->status;
       memcpy(h + leaf_off[cls] + (size_t)lfill[cls] * sizeof(LeafArgs), &la, sizeof la);
       reinterpret_cast<uint32_t*>(h + wpre_off[cls])[lfill[cls]] = lwg[cls];
       ++lfill[cls];

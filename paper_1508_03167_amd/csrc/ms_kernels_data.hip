@@ -18,7 +18,9 @@
 // with up(x) = min{r' > x : j_r' = x} and top() following up() to its end:
 //   F[r] = T0[top(nxt(r))] if nxt(r) = min{r' > r : j_r' = j_r} exists,
 //          T0[j_r] otherwise;     F[0] = T0[top(0)].
-// The lists of steps per target slot are built with LDS atomic exchanges.
+// The steps that target a slot are chained in increasing order by atomic
+// exchanges on the slot's LDS word, so up() and nxt() come straight from the
+// exchanges' return values; top() is found by pointer jumping.
 //
 // Insertion loop in LDS.  A merge's tail steps i = P..N-1 run as groups of
 // 64 steps on one wave: within a group each lane resolves its step against
@@ -69,19 +71,20 @@ __device__ __forceinline__ uint32_t get16(uint32_t packed, int half) { return (p
 
 // Fisher-Yates of every leaf of the super-block at once (Algorithm 1 per leaf).
 // Before the elements are loaded, the LDS data region holds one 32-bit word
-// per super-block slot: a 16-bit list head (steps targeting the slot, later
-// up()) and a 16-bit list link (later nxt()).  Each thread owns blocks of 4 consecutive steps of one
-// leaf (the steps whose draws share one Philox block) and returns, packed two
-// per register, the leaf-relative source F of each of its slots.
+// per super-block slot: first the slot's draw, then a 16-bit list head
+// (later up()) and the step's 16-bit link (later nxt(), or its draw when no
+// later step targets the same slot).  Each thread owns blocks of 4
+// consecutive steps of one leaf (the steps whose draws share one Philox
+// block) and returns, packed two per register, the leaf-relative source F of
+// each of its slots.
 template <int BPT, int NT>
-__device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, uint32_t lb, uint32_t b, uint32_t u,
-                                                uint32_t lt, uint32_t tpl, uint32_t cnt, Key key, uint32_t* bits,
+__device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uint32_t b, uint32_t u, uint32_t lt,
+                                                uint32_t tpl, uint32_t cnt, Key key, uint32_t* bits, uint32_t* status,
                                                 uint32_t (&F)[BPT][2]) {
   constexpr uint32_t NONE = 0xFFFFu;
   uint16_t* const half = head;  // the lists' words, as 16-bit halves
 #define HED(y) half[2 * (y)]
 #define LNK(y) half[2 * (y) + 1]
-  uint32_t J[BPT][2];
   // 1. the draws j_r, r = 1..b-1, of this thread's blocks (r = 4g..4g+3,
   //    g = lt + tpl*k).  The primary words go to the data region first (one
   //    word per slot); then each lane runs the Fast Dice Roller of its draws
@@ -169,106 +172,89 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
       }
     }
   }
+  __syncthreads();
+  // 2. up(x) = least step > x targeting x, nxt(r) = least step > r
+  //    targeting j_r.  One 32-bit word per super-block slot y: the high half
+  //    holds j_y while the steps are pushed onto their slots' lists, the low
+  //    half the head of y's list.  A push of step r is an atomic exchange of
+  //    word j_r that keeps its high half, so the old head comes back.  The
+  //    steps of a leaf are pushed in increasing order (each wave of the leaf
+  //    takes one contiguous range of steps, the waves one after the other,
+  //    a wave's lanes in step order; the LDS applies one wave's exchanges of
+  //    one address in lane order), so the head a push returns is the
+  //    previous step targeting the same slot: its nxt() is the pushed step,
+  //    and the first push onto slot y gives up(y) (the second one when the
+  //    first is step y itself).  No list is walked.  Pushes per lane: at most
+  //    ceil(ceil(b / ranges) / lanes) <= SCAP / NT + 1 <= 4 * BPT, since a
+  //    leaf holds at most SCAP / 2^lds_levels + 1 slots.
+  // (each thread rewrites the words of its own steps: j_r, none for step 0)
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
     const uint32_t g = lt + tpl * k;
-    uint32_t jj[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const uint32_t r = 4 * g + e;
-      jj[e] = (r >= 1 && r < b) ? W[lb + r] : NONE;
+      if (r < b) W[lb + r] = ((r >= 1 ? W[lb + r] : NONE) << 16) | NONE;
     }
-    J[k][0] = jj[0] | (jj[1] << 16);
-    J[k][1] = jj[2] | (jj[3] << 16);
   }
   __syncthreads();
-  // Lists in LDS: one 32-bit word per super-block slot y, its low half the
-  // head of y's list (later up(y)), its high half the link of step y (later
-  // nxt(y)).  Pushing r onto the list of slot j_r is one atomic exchange of
-  // the word (low half r): lanes that push onto one slot at once each get
-  // the head left by the one before them, so no push is ever retried.  The
-  // links wait in registers until every push is done.
-  for (uint32_t i = threadIdx.x; i < cnt; i += NT) W[i] = 0xFFFFFFFFu;
-  __syncthreads();
-  {
-    uint32_t LK[BPT][2];
+  constexpr int ITER = 4 * BPT;  // pushes per lane, at most
+  const uint32_t lpp = tpl < 64 ? tpl : 64u;  // lanes pushing one range
+  const uint32_t wpl = tpl / lpp;             // ranges (waves) per leaf
+  const uint32_t wl = lt / lpp, li = lt % lpp;
+  const uint32_t span = (((b + wpl - 1) / wpl + lpp - 1) / lpp) * lpp;
+  const uint32_t r0 = wl * span + li;
+  const uint32_t r1 = min(b, (wl + 1) * span);
+  uint32_t OLD[(ITER + 1) / 2];  // per pushed step, packed two per register: the head it replaced
+  for (uint32_t ph = 0; ph < wpl; ++ph) {
+    if (wl == ph) {
 #pragma unroll
-    for (int k = 0; k < BPT; ++k) {
-      const uint32_t g = lt + tpl * k;
-      uint32_t lk[4] = {NONE, NONE, NONE, NONE};
-      if (4 * g < b) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const uint32_t jx = get16(J[k][e >> 1], e & 1);
-          if (jx != NONE) lk[e] = atomicExch(&W[lb + jx], 0xFFFF0000u | (4 * g + e)) & 0xFFFFu;
+      for (int t = 0; t < ITER; ++t) {
+        const uint32_t r = r0 + lpp * t;
+        uint32_t old = NONE;
+        if (r >= 1 && r < r1) {
+          const uint32_t y = W[lb + r] >> 16;
+          const uint32_t hi = W[lb + y] & 0xFFFF0000u;
+          old = atomicExch(&W[lb + y], hi | r) & 0xFFFFu;
         }
+        if (t & 1) OLD[t >> 1] |= old << 16;
+        else OLD[t >> 1] = old;
+        // at most four pushes' loads in flight (register pressure)
+        if ((t & 3) == 3) asm volatile("" ::: "memory");
       }
-      LK[k][0] = lk[0] | (lk[1] << 16);
-      LK[k][1] = lk[2] | (lk[3] << 16);
     }
     __syncthreads();
+  }
+  // The first push onto slot y sets up(y), unless it is step y itself: then
+  // the second push (if any) does.  A pushed step's link starts as its own
+  // target j_r with bit 15 set (no later step on its slot: its source is
+  // j_r; j_r = r marks a self push); the step pushed next onto the same slot
+  // then makes itself the link.
+  constexpr uint32_t NOLATER = 0x8000u;
 #pragma unroll
-    for (int k = 0; k < BPT; ++k) {
-      const uint32_t g = lt + tpl * k;
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (4 * g + e < b) LNK(lb + 4 * g + e) = (uint16_t)get16(LK[k][e >> 1], e & 1);
+  for (int t = 0; t < ITER; ++t) {
+    const uint32_t r = r0 + lpp * t;
+    if (r >= 1 && r < r1) {
+      const uint32_t old = get16(OLD[t >> 1], t & 1);
+      const uint32_t y = W[lb + r] >> 16;
+      if (old == NONE) HED(lb + y) = (uint16_t)(r != y ? r : NONE);
+      LNK(lb + r) = (uint16_t)(y | NOLATER);
     }
   }
   __syncthreads();
-  // 2. up(x) = least step > x targeting x; nxt(r) = least step > r targeting j_r
-  uint32_t U[BPT][2], X[BPT][2];
 #pragma unroll
-  for (int k = 0; k < BPT; ++k) {
-    const uint32_t g = lt + tpl * k;
-    U[k][0] = U[k][1] = X[k][0] = X[k][1] = 0xFFFFFFFFu;
-    if (4 * g < b) {
-      uint32_t pu[4], px[4], bu[4], bx[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint32_t x = 4 * g + e;
-        const uint32_t jx = get16(J[k][e >> 1], e & 1);
-        pu[e] = x < b ? (uint32_t)HED(lb + x) : NONE;
-        px[e] = (x >= 1 && x < b) ? (uint32_t)HED(lb + jx) : NONE;
-        bu[e] = NONE;
-        bx[e] = NONE;
+  for (int t = 0; t < ITER; ++t) {
+    const uint32_t r = r0 + lpp * t;
+    if (r >= 1 && r < r1) {
+      const uint32_t old = get16(OLD[t >> 1], t & 1);
+      if (old != NONE) {
+        // pushes onto one slot came in increasing step order; a lane that
+        // sees otherwise reports it (bit 3), the lists are then unordered
+        if (old > r) atomicOr(status, 8u);
+        if (LNK(lb + old) == (old | NOLATER)) HED(lb + old) = (uint16_t)r;
+        LNK(lb + old) = (uint16_t)r;
       }
-      // walk the eight lists side by side
-      for (;;) {
-        bool any = false;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const uint32_t x = 4 * g + e;
-          if (pu[e] != NONE) {
-            any = true;
-            if (pu[e] > x && pu[e] < bu[e]) bu[e] = pu[e];
-            pu[e] = LNK(lb + pu[e]);
-          }
-          if (px[e] != NONE) {
-            any = true;
-            if (px[e] > x && px[e] < bx[e]) bx[e] = px[e];
-            px[e] = LNK(lb + px[e]);
-          }
-        }
-        if (!any) break;
-      }
-      U[k][0] = bu[0] | (bu[1] << 16);
-      U[k][1] = bu[2] | (bu[3] << 16);
-      X[k][0] = bx[0] | (bx[1] << 16);
-      X[k][1] = bx[2] | (bx[3] << 16);
     }
-  }
-  __syncthreads();
-  // 3. the low halves now hold up(x) and the high halves nxt(r)
-#pragma unroll
-  for (int k = 0; k < BPT; ++k) {
-    const uint32_t g = lt + tpl * k;
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (4 * g + e < b) {
-        HED(lb + 4 * g + e) = (uint16_t)get16(U[k][e >> 1], e & 1);
-        LNK(lb + 4 * g + e) = (uint16_t)get16(X[k][e >> 1], e & 1);
-      }
   }
   __syncthreads();
   // 4. top() of every slot by pointer jumping over the up() links (each
@@ -323,12 +309,17 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint16_t* link, 
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const uint32_t x = 4 * g + e;
-        const uint32_t nx = x < b ? (uint32_t)LNK(lb + x) : NONE;
-        const uint32_t t = x == 0 ? 0u : nx;
-        f[e] = get16(J[k][e >> 1], e & 1);
-        if (x < b && (x == 0 || nx != NONE)) {
-          const uint32_t top = HED(lb + t);
-          f[e] = top != NONE ? top : t;
+        // step x's link: a later step on its slot, or its own target with
+        // bit 15 set; slot 0 starts from itself
+        const uint32_t lk = x >= 1 && x < b ? (uint32_t)LNK(lb + x) : 0u;
+        f[e] = 0u;
+        if (x < b) {
+          if (lk & NOLATER) {
+            f[e] = lk & ~NOLATER;
+          } else {
+            const uint32_t top = HED(lb + lk);
+            f[e] = top != NONE ? top : lk;
+          }
         }
       }
       F[k][0] = (f[0] & 0xFFFFu) | (f[1] << 16);
@@ -450,9 +441,8 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
   const uint32_t lb = (uint32_t)(bound(a.n, u, a.c) - base);
   const uint32_t b = (uint32_t)(bound(a.n, u + 1, a.c) - bound(a.n, u, a.c));
   uint16_t* head = reinterpret_cast<uint16_t*>(data);
-  uint16_t* link = head + SCAP;
   uint32_t F[BPT][2];
-  leaf_fy_sources<BPT, NT>(head, link, lb, b, (uint32_t)u, lt, tpl, cnt, key, &bits, F);
+  leaf_fy_sources<BPT, NT>(head, lb, b, (uint32_t)u, lt, tpl, cnt, key, &bits, a.status, F);
   (void)nleaf;
 
   for (uint32_t i = tid; i < cnt; i += NT) data[i] = IDENT ? ident_value<E>(base + i) : in[base + i];

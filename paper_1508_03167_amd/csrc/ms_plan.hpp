@@ -108,6 +108,7 @@ struct LeafArgs {
   uint32_t lds_levels;
   uint32_t key0, key1;
   unsigned long long* bits;
+  uint32_t* status;  // device status flags (bit 3: list order check)
 };
 
 struct PassArgs {
