@@ -1,0 +1,48 @@
+"""GPU parity under the library's tuning knobs, each read once per process
+(so each runs in a child process): the 1024-thread leaf with 128 KiB
+super-blocks (MS_LEAF_BIG=1) and 2048-slot fused-pass tiles
+(MS_GROUP_TILE=2048).  The permutation must not depend on either."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+CHILD = r"""
+import sys
+sys.path.insert(0, %r)
+import numpy as np, torch
+import paper_1508_03167_amd as M
+from oracle import oracle as O
+for n, seed, eb in [(70001, 3, 4), ((1 << 20) + 3, 4, 4), (3_000_017, 5, 4), (300_007, 6, 8), (123_457, 7, 16)]:
+    want, wbits = O.permutation(n, 4096, seed)
+    bits = torch.zeros(1, dtype=torch.int64, device="cuda")
+    if eb == 4:
+        x = torch.empty(n, dtype=torch.int32, device="cuda")
+        M.permutation(x, seed, bits=bits)
+        got = x.cpu().numpy().view(np.uint32)
+        ok = np.array_equal(got, want)
+    else:
+        host = np.random.default_rng(eb).integers(0, 2**63, size=(n, eb // 8), dtype=np.int64)
+        x = torch.from_numpy(host.copy()).cuda()
+        M.shuffle_(x, seed, bits=bits)
+        ok = np.array_equal(x.cpu().numpy(), host[want.astype(np.int64)])
+    torch.cuda.synchronize()
+    status = M.device_status()
+    print("case", n, eb, "ok" if ok and int(bits.item()) == wbits and status == 0 else "BAD", flush=True)
+"""
+
+
+@pytest.mark.parametrize("knob", [{"MS_LEAF_BIG": "1"}, {"MS_GROUP_TILE": "2048"}])
+def test_tuning_knob_keeps_the_permutation(knob):
+    print(f"[gpu] knob {knob}", flush=True)
+    env = dict(os.environ, **knob)
+    r = subprocess.run([sys.executable, "-c", CHILD % os.path.dirname(HERE)], env=env, capture_output=True,
+                       text=True, timeout=300)
+    lines = [l for l in r.stdout.splitlines() if l.startswith("case")]
+    assert r.returncode == 0 and len(lines) == 5, (r.stdout, r.stderr[-2000:])
+    assert all(l.endswith(" ok") for l in lines), r.stdout
