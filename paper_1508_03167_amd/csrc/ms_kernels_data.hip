@@ -258,73 +258,86 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uin
   }
   __syncthreads();
   // 4. top() of every slot by pointer jumping over the up() links (each
-  //    round halves the remaining chain), then F[r] = top(nxt(r)) or j_r,
-  //    F[0] = top(0)
-  //    A slot whose pointer is NONE or points at a chain end is final and
-  //    drops out of the later rounds.
+  //    round halves the remaining chains), then F[r] = top(nxt(r)) or j_r,
+  //    F[0] = top(0).  F first takes each slot's link (nxt(x), or j_x with
+  //    bit 15 set), which frees the high halves: the jumping then reads one
+  //    half and writes the other, one barrier per round.  A slot whose
+  //    pointer is NONE or points at a chain end is final; it writes its value
+  //    to both halves and drops out of the later rounds.
   static_assert(4 * BPT <= 64, "live slots are tracked in a 64-bit mask");
-  uint64_t live = ~0ull;
-  for (;;) {
-    uint32_t nt[BPT][2];
-    uint64_t upd = 0;
-#pragma unroll
-    for (int k = 0; k < BPT; ++k) {
-      const uint32_t g = lt + tpl * k;
-      nt[k][0] = nt[k][1] = 0u;
-      uint32_t v[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint32_t x = 4 * g + e;
-        const uint64_t bit = 1ull << (4 * k + e);
-        if ((live & bit) && x < b) {
-          const uint32_t t = HED(lb + x);
-          const uint32_t tt = t != NONE ? (uint32_t)HED(lb + t) : NONE;
-          if (tt != NONE) {
-            v[e] = tt;
-            upd |= bit;
-          }
-        }
-      }
-      nt[k][0] = (v[0] & 0xFFFFu) | (v[1] << 16);
-      nt[k][1] = (v[2] & 0xFFFFu) | (v[3] << 16);
-    }
-    live = upd;
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < BPT; ++k) {
-      const uint32_t g = lt + tpl * k;
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (upd & (1ull << (4 * k + e))) HED(lb + 4 * g + e) = (uint16_t)get16(nt[k][e >> 1], e & 1);
-    }
-    if (!__syncthreads_or(upd != 0)) break;
-  }
-  // the low half of x's word is now the end of x's up() chain, or NONE if x has no up()
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
     const uint32_t g = lt + tpl * k;
-    F[k][0] = F[k][1] = 0u;
-    if (4 * g < b) {
-      uint32_t f[4];
+    uint32_t lk[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint32_t x = 4 * g + e;
-        // step x's link: a later step on its slot, or its own target with
-        // bit 15 set; slot 0 starts from itself
-        const uint32_t lk = x >= 1 && x < b ? (uint32_t)LNK(lb + x) : 0u;
-        f[e] = 0u;
-        if (x < b) {
-          if (lk & NOLATER) {
-            f[e] = lk & ~NOLATER;
-          } else {
-            const uint32_t top = HED(lb + lk);
-            f[e] = top != NONE ? top : lk;
-          }
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t x = 4 * g + e;
+      lk[e] = x >= 1 && x < b ? (uint32_t)LNK(lb + x) : 0u;
+    }
+    F[k][0] = lk[0] | (lk[1] << 16);
+    F[k][1] = lk[2] | (lk[3] << 16);
+  }
+  __syncthreads();
+  uint64_t live = 0;
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const uint32_t g = lt + tpl * k;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t x = 4 * g + e;
+      if (x < b) {
+        const uint32_t t = HED(lb + x);
+        const uint32_t tt = t != NONE ? (uint32_t)HED(lb + t) : NONE;
+        LNK(lb + x) = (uint16_t)(tt != NONE ? tt : t);
+        if (tt != NONE) live |= 1ull << (4 * k + e);
+      }
+    }
+  }
+  bool rd_high = true;  // this round reads the high halves
+  while (__syncthreads_or(live != 0)) {
+    uint64_t m = live, nl = 0;
+    while (m) {
+      const int q = __builtin_ctzll(m);
+      m &= m - 1;
+      const uint32_t x = lb + 4 * (lt + tpl * (uint32_t)(q >> 2)) + (uint32_t)(q & 3);
+      uint16_t* rd = rd_high ? &LNK(0) : &HED(0);
+      uint16_t* wr = rd_high ? &HED(0) : &LNK(0);
+      const uint32_t t = rd[2 * x];
+      const uint32_t tt = rd[2 * (lb + t)];
+      if (tt == NONE) {
+        wr[2 * x] = (uint16_t)t;
+        rd[2 * x] = (uint16_t)t;
+      } else {
+        wr[2 * x] = (uint16_t)tt;
+        nl |= 1ull << q;
+      }
+    }
+    live = nl;
+    rd_high = !rd_high;
+  }
+  // both halves of x's word now hold the end of x's up() chain, or NONE if x has no up()
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const uint32_t g = lt + tpl * k;
+    uint32_t f[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t x = 4 * g + e;
+      // step x's link: a later step on its slot, or its own target with
+      // bit 15 set; slot 0 starts from itself
+      const uint32_t lk = get16(F[k][e >> 1], e & 1);
+      f[e] = 0u;
+      if (x < b) {
+        if (lk & NOLATER) {
+          f[e] = lk & ~NOLATER;
+        } else {
+          const uint32_t top = HED(lb + lk);
+          f[e] = top != NONE ? top : lk;
         }
       }
-      F[k][0] = (f[0] & 0xFFFFu) | (f[1] << 16);
-      F[k][1] = (f[2] & 0xFFFFu) | (f[3] << 16);
     }
+    F[k][0] = (f[0] & 0xFFFFu) | (f[1] << 16);
+    F[k][1] = (f[2] & 0xFFFFu) | (f[3] << 16);
   }
   __syncthreads();
 #undef HED
