@@ -551,7 +551,9 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
     // break step shares one flip word pair: with o_j the ones among its
     // first j flips, slot j takes B at n1 + t0 - r0 + o_j or A at r0 + j - o_j
     constexpr int KG = (KS + 3) / 4;
-    uint32_t SRC[2 * KG];
+    using R = typename RegOf<E>::type;
+    R* dataR = reinterpret_cast<R*>(data);
+    R val[4 * KG];
 #pragma unroll
     for (int q = 0; q < KG; ++q) {
       const uint32_t s0 = 4 * (tv + q * NT);
@@ -604,18 +606,10 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
           }
         }
       }
-      SRC[2 * q] = src[0] | (src[1] << 16);
-      SRC[2 * q + 1] = src[2] | (src[3] << 16);
-    }
-    using R = typename RegOf<E>::type;
-    R* dataR = reinterpret_cast<R*>(data);
-    R val[4 * KG];
-#pragma unroll
-    for (int q = 0; q < KG; ++q) {
-      const uint32_t s0 = 4 * (tv + q * NT);
+      // the values can be read at once: nothing is written before the barrier
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (s0 + j < cnt) val[4 * q + j] = dataR[get16(SRC[2 * q + (j >> 1)], j & 1)];
+        if (s0 + j < cnt) val[4 * q + j] = dataR[src[j]];
     }
     __syncthreads();
     asm volatile("" : "+v"(tv));
