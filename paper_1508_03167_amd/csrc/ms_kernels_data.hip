@@ -455,7 +455,16 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
   const uint32_t b = (uint32_t)(bound(a.n, u + 1, a.c) - bound(a.n, u, a.c));
   uint16_t* head = reinterpret_cast<uint16_t*>(data);
   uint32_t F[BPT][2];
+  // touch one word of every 128-byte line of the super-block's input now, so
+  // that the load after the Fisher-Yates phase finds it in L2
+  uint32_t touch = 0;
+  if (!IDENT) {
+    const uint32_t per_line = 128 / sizeof(E);
+    const uint32_t line = (uint32_t)tid * per_line;
+    if (line < cnt) touch = *reinterpret_cast<const uint32_t*>(in + base + line);
+  }
   leaf_fy_sources<BPT, NT>(head, lb, b, (uint32_t)u, lt, tpl, cnt, key, &bits, a.status, F);
+  asm volatile("" ::"v"(touch));
   (void)nleaf;
 
   for (uint32_t i = tid; i < cnt; i += NT) data[i] = IDENT ? ident_value<E>(base + i) : in[base + i];
