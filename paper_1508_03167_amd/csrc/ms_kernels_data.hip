@@ -350,7 +350,7 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uin
 // disjoint slots, so its swaps commute and run at once; other groups resolve
 // their steps against each other lane by lane.
 template <typename E>
-__device__ __forceinline__ void lds_merge_tail(E* data, uint32_t* seen, uint32_t s0, uint32_t N, uint32_t P,
+__device__ __forceinline__ void lds_merge_tail(E* data, uint32_t* seen, uint32_t* dup, uint32_t s0, uint32_t N, uint32_t P,
                                                uint32_t L, uint32_t gm, Key key, uint32_t* bits) {
   const int lane = threadIdx.x & 63;
   for (uint32_t i0 = P; i0 < N; i0 += 64) {
@@ -383,15 +383,25 @@ __device__ __forceinline__ void lds_merge_tail(E* data, uint32_t* seen, uint32_t
       }
       continue;
     }
+    // Only lanes that target a slot of the group, or share their target with
+    // another lane, can depend on one another: a lane that found its
+    // target's bit already set marks the slot in `dup`, which tells the first
+    // lane on that slot too.  Those lanes are the only ones scanned.
+    const uint32_t bit = 1u << ((s0 + j) & 31);
+    const bool later_dup = act && j < i0 && clash;
+    if (later_dup) atomicOr(&dup[(s0 + j) >> 5], bit);
+    const bool first_dup = act && j < i0 && !clash && (dup[(s0 + j) >> 5] & bit) != 0;
+    const uint64_t S = __ballot(act && (j >= i0 || later_dup || first_dup));
+    if (later_dup) atomicAnd(&dup[(s0 + j) >> 5], ~bit);
     int candY = -1, tgtLater = -1;
     bool lastForJ = true;
-    const uint32_t nact = (N - i0) < 64u ? (N - i0) : 64u;
-    for (uint32_t q = 0; q < nact; ++q) {
-      const uint32_t jq = (uint32_t)__builtin_amdgcn_readlane((int)j, (int)q);
-      const uint32_t iq = i0 + q;
-      if ((int)q < lane && jq == j && iq != j) candY = (int)q;
-      if ((int)q > lane && jq == i) tgtLater = (int)q;
-      if ((int)q > lane && jq == j) lastForJ = false;
+    for (uint64_t m = S; m != 0; m &= m - 1) {
+      const int q = __builtin_ctzll(m);
+      const uint32_t jq = (uint32_t)__builtin_amdgcn_readlane((int)j, q);
+      const uint32_t iq = i0 + (uint32_t)q;
+      if (q < lane && jq == j && iq != j) candY = q;
+      if (q > lane && jq == i) tgtLater = q;
+      if (q > lane && jq == j) lastForJ = false;
     }
     // value slot i fetches from slot j at its step: a lane index or a slot
     int ref = -1;
@@ -644,11 +654,12 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
     // insertion loops, one wave per merge; the flip words are dead now and
     // their space holds the slot bitmap
     uint32_t* seen = maux.words;
-    for (uint32_t w = tid; w < (cnt + 31) / 32; w += NT) seen[w] = 0u;
+    uint32_t* dup = maux.wpre;
+    for (uint32_t w = tid; w < (cnt + 31) / 32; w += NT) seen[w] = dup[w] = 0u;
     __syncthreads();
     for (uint32_t mm = tid >> 6; mm < nm; mm += NT / 64) {
       const uint32_t gm = (uint32_t)((sb << (Lam - L)) + mm);
-      lds_merge_tail<E>(data, seen, mb[mm], mb[mm + 1] - mb[mm], mP[mm] >> 1, L, gm, key, &bits);
+      lds_merge_tail<E>(data, seen, dup, mb[mm], mb[mm + 1] - mb[mm], mP[mm] >> 1, L, gm, key, &bits);
     }
     __syncthreads();
   }
