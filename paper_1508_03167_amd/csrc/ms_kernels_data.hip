@@ -219,8 +219,6 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uin
         }
         if (t & 1) OLD[t >> 1] |= old << 16;
         else OLD[t >> 1] = old;
-        // at most four pushes' loads in flight (register pressure)
-        if ((t & 3) == 3) asm volatile("" ::: "memory");
       }
     }
     __syncthreads();
