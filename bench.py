@@ -230,7 +230,7 @@ def main():
         print(json.dumps({"copy_calibration_bytes_per_dispatch": 1 << 30}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (no multi-GPU path)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 (no multi-GPU path)"}))
         sys.exit(2)
 
     import torch

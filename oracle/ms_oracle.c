@@ -6,13 +6,13 @@
  * load or call this file: only tests/, the package's smoke() entry and the
  * cpu_baseline leg of bench.py use it.  It shares no code with the HIP
  * library under paper_1508_03167_amd/csrc (own Philox, own bounded draw,
- * own Fisher-Yates, own Merge, own driver).
+ * own Fisher-Yates, own Merge, own top-level routine).
  *
  * What it computes (each function cites the passage it follows):
  *   - Fisher-Yates shuffle, descending, j uniform in {0..i}   (Algorithm 1)
  *   - Merge of two shuffled adjacent ranges                    (Algorithm 2,
  *     Section 1.1, and the merge() listing of Appendix A.1)
- *   - the MergeShuffle driver: c = least c with (n >> c) <= cutoff, q = 2^c
+ *   - the MergeShuffle top-level routine: c = least c with (n >> c) <= cutoff, q = 2^c
  *     blocks [n*i/q, n*(i+1)/q), Fisher-Yates per block, then merges of
  *     adjacent blocks level by level                          (Algorithm
  *     MergeShuffle, Section 1; shuffle() listing of Appendix A.2)

@@ -1,7 +1,7 @@
 // ms_api.hip -- host runtime and C ABI of the MergeShuffle library.
 //
 // The planner turns (n, element size, cutoff) into the level layout of the
-// driver (shuffle() listing, Appendix A.2): c levels over q = 2^c leaves, the
+// top-level routine (shuffle() listing, Appendix A.2): c levels over q = 2^c leaves, the
 // first `lds_levels` merge levels fused into the leaf kernel, the rest as HBM
 // passes with their data-independent plan.  Scratch (one array copy for the
 // out-of-place HBM levels plus the plan tables) is kept per (device, stream)

@@ -2,7 +2,7 @@
 
 Philox is pinned against values the generator's authors publish and against
 PyTorch's independent host implementation.  The stream rule (which Philox
-word and bit a flip or a bounded draw reads) is this build's own convention
+word and bit a flip or a bounded draw reads) is this implementation's own convention
 for a paper that names no generator; its test states the rule once more.
 """
 import os

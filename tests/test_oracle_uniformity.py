@@ -3,10 +3,10 @@
 * exact: enumerate every outcome of every coin flip (probability 1/2) and
   every bounded draw (probability 1/k) for n <= 6 and several cutoffs; each
   of the n! permutations must get probability exactly 1/n! (Lemma 1 applied
-  level by level; with cutoff >= n the driver is Algorithm 1 alone);
+  level by level; with cutoff >= n the top-level routine is Algorithm 1 alone);
 * statistical: seeded runs through the Philox streams, chi-square over all of
   S_n for small n and over position marginals for larger n;
-* structural: the driver's partition (Appendix A.2: c, q, block bounds).
+* structural: the top-level routine's partition (Appendix A.2: c, q, block bounds).
 """
 import math
 from collections import defaultdict
