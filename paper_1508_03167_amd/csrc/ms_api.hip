@@ -254,6 +254,10 @@ struct Arena {
   size_t stage_bytes[2] = {0, 0};
   hipEvent_t stage_done[2] = {nullptr, nullptr};
   int stage_next = 0;
+  // the plan runs on its own stream (default priority), forked from and
+  // joined back into this one, so that it overlaps the leaf kernel
+  hipStream_t plan_st = nullptr;
+  hipEvent_t plan_fork = nullptr, plan_join = nullptr;
 };
 
 constexpr int kSideStreams = 4;
@@ -422,10 +426,25 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
   pa.key1 = (uint32_t)(seed >> 32);
   pa.bits = bits;
   pa.status = dc->status;
+  bool plan_forked = false;
   if (hp.nlev) {
     bind_plan(hp, ar.plan);
-    ProfScope ps(0, st);
-    launch_plan(pa, st);
+    // the plan depends only on (n, cutoff, seed), the leaf kernel only on
+    // the data: the plan goes to the arena's plan stream and the first HBM
+    // pass waits for it
+    if (!ar.plan_st) {
+      HIP_TRY(hipStreamCreateWithFlags(&ar.plan_st, hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&ar.plan_fork, hipEventDisableTiming));
+      HIP_TRY(hipEventCreateWithFlags(&ar.plan_join, hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventRecord(ar.plan_fork, st));
+    HIP_TRY(hipStreamWaitEvent(ar.plan_st, ar.plan_fork, 0));
+    {
+      ProfScope ps(0, ar.plan_st);
+      launch_plan(pa, ar.plan_st);
+    }
+    HIP_TRY(hipEventRecord(ar.plan_join, ar.plan_st));
+    plan_forked = true;
   }
   void* X = ptr;
   void* Y = ar.data;
@@ -445,6 +464,7 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
     ProfScope ps(1, st);
     launch_leaf(la, eb, ident, hp.q >> hp.lam, st);
   }
+  if (plan_forked) HIP_TRY(hipStreamWaitEvent(st, ar.plan_join, 0));
   for (uint32_t g = 0; hp.fused && g < hp.ngroup; ++g) {
     void* other = cur == X ? Y : X;
     const GroupInfo& gi = pa.grp[g];
@@ -865,8 +885,17 @@ int ms_release(void) {
   HIP_TRY(hipDeviceSynchronize());
   DeviceCtx& d = g_dev[dev];
   for (auto& kv : d.arenas) {
-    if (kv.second.data) HIP_TRY(hipFree(kv.second.data));
-    if (kv.second.plan) HIP_TRY(hipFree(kv.second.plan));
+    Arena& ar = kv.second;
+    if (ar.data) HIP_TRY(hipFree(ar.data));
+    if (ar.plan) HIP_TRY(hipFree(ar.plan));
+    if (ar.wave) HIP_TRY(hipFree(ar.wave));
+    for (int i = 0; i < 2; ++i) {
+      if (ar.stage[i]) HIP_TRY(hipHostFree(ar.stage[i]));
+      if (ar.stage_done[i]) HIP_TRY(hipEventDestroy(ar.stage_done[i]));
+    }
+    if (ar.plan_fork) HIP_TRY(hipEventDestroy(ar.plan_fork));
+    if (ar.plan_join) HIP_TRY(hipEventDestroy(ar.plan_join));
+    if (ar.plan_st) HIP_TRY(hipStreamDestroy(ar.plan_st));
   }
   d.arenas.clear();
   return MS_OK;
