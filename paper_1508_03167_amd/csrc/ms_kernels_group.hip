@@ -44,7 +44,10 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, uint32_t tile) {
   constexpr int TB = T + 4 * (1 << LAM);
   __shared__ __align__(16) E buf[2][TB];
   __shared__ __align__(16) uint32_t words[NWORD];
-  __shared__ uint32_t wpre[NWORD];
+  // zeros before each flip word: 16 bits suffice, which keeps the 4-level
+  // tile within a quarter of the CU's LDS (four workgroups per CU)
+  static_assert(32 * NWORD < 65536, "flip-word prefix must fit 16 bits");
+  __shared__ uint16_t wpre[NWORD];
   __shared__ uint32_t tmp[NT / 64 + 1];
   __shared__ __align__(16) uint32_t hot[NODES][8];
   __shared__ Win win[NODES + 1];
@@ -269,7 +272,7 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, uint32_t tile) {
 #pragma unroll
     for (int k = 0; k < KW; ++k) {
       const uint32_t wi = tid * KW + k;
-      if (wi < NWORD) wpre[wi] = run;
+      if (wi < NWORD) wpre[wi] = (uint16_t)run;
       run += zl[k];
     }
   }
@@ -429,8 +432,11 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t ntiles) {
   return x * q + min(x, r) + i;
 }
 
+// The 4-level tile is asked to fit 64 VGPRs (8 waves per SIMD, as its LDS
+// allows); the others fit by themselves.
 template <typename E, int T, int LAM, int NT>
-__global__ void __launch_bounds__(NT) group_kernel(GroupArgs a) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(LAM == 4 ? 8 : 1)))
+group_kernel(GroupArgs a) {
   if (blockIdx.x >= a.ntiles) return;
   group_body<E, T, LAM, NT>(a, xcd_tile(a.ntiles));
 }
@@ -438,7 +444,7 @@ __global__ void __launch_bounds__(NT) group_kernel(GroupArgs a) {
 // The same pass of many arrays in one launch: job j owns tiles
 // [tpre[j], tpre[j+1]) of the ntiles = tpre[njobs] tiles.
 template <typename E, int T, int LAM, int NT>
-__global__ void __launch_bounds__(NT) group_multi_kernel(const GroupArgs* __restrict__ jobs,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(LAM == 4 ? 8 : 1))) group_multi_kernel(const GroupArgs* __restrict__ jobs,
                                                          const uint32_t* __restrict__ tpre, uint32_t njobs,
                                                          uint32_t ntiles) {
   if (blockIdx.x >= ntiles) return;
