@@ -4,7 +4,7 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--n-log2 30] [--no-cpu-base
 
 A step is one complete shuffle of the resident 4 GiB array: the plan, the
 leaf kernel (Fisher-Yates of every leaf plus the merge levels that fit in
-LDS) and the HBM merge passes (each runs up to three merge levels, their
+LDS) and the HBM merge passes (each runs three or four merge levels, their
 insertion loops included).  The JSON line carries the whole-job throughput
 (Gelem/s), the roofline of the kernel class that takes most of the step
 (measured with HIP events around each launch on the library's stream), and
@@ -131,6 +131,55 @@ def bench_r1(M, torch, n_log2: int = 26, seed: int = 7, reps: int = 5):
             "stable_one_level_hbm_only_ms": round(t2 * 1e3, 3), "default_path_ms": round(t0 * 1e3, 3)}
 
 
+def _timed_classes(M, torch, fn, reps: int):
+    """Wall time per call of fn() and the library's per-class kernel times."""
+    fn()
+    torch.cuda.synchronize()
+    M.profile_read()
+    M.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    M.profile_enable(False)
+    ms, cnt = M.profile_read()
+    return dt, ms, cnt
+
+
+def bench_records(M, torch, n_log2: int = 27, seed: int = 11, reps: int = 5):
+    """16-byte records {uint64 key from a seeded stream, uint64 payload = index},
+    shuffled whole (the same permutation as the uint32 index array)."""
+    from paper_1508_03167_amd.inputs import records16
+
+    n = 1 << n_log2
+    rec = torch.from_numpy(records16(n, seed).view(np.int64)).to("cuda:0")
+    dt, ms, cnt = _timed_classes(M, torch, lambda: M.shuffle_(rec, seed), reps)
+    del rec
+    launches = max(cnt["merge_pass"], 1)
+    avg = ms["merge_pass"] / launches
+    gbs = 2.0 * n * 16 / (avg / 1e3) / 1e9
+    return {"workload": f"MergeShuffle of 2^{n_log2} 16-byte records (uint64 key from a seeded stream, "
+                        f"uint64 payload = index), seed {seed}, cutoff 4096",
+            "n": n, "record_bytes": 16, "ms": round(dt * 1e3, 3), "gelem_s": round(n / dt / 1e9, 3),
+            "merge_pass_avg_ms": round(avg, 4), "merge_passes": cnt["merge_pass"] // reps,
+            "merge_pass_gb_s": round(gbs, 1), "merge_pass_frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4),
+            "ms_by_kernel_class": {k: round(v / reps, 3) for k, v in ms.items()}}
+
+
+def bench_small(M, torch, n_log2: int = 20, seed: int = 1, reps: int = 200):
+    """The small plain-permutation case: a uint32 identity array of 2^20
+    elements (4 MiB, resident in the caches), one call after another."""
+    n = 1 << n_log2
+    x = torch.arange(n, dtype=torch.int32, device="cuda:0")
+    dt, ms, cnt = _timed_classes(M, torch, lambda: M.shuffle_(x, seed), reps)
+    del x
+    return {"workload": f"MergeShuffle of one uint32 identity array, n=2^{n_log2}, seed {seed}, cutoff 4096",
+            "n": n, "ms": round(dt * 1e3, 4), "gelem_s": round(n / dt / 1e9, 3),
+            "launches_per_call": {k: round(v / reps, 2) for k, v in cnt.items()},
+            "ms_by_kernel_class": {k: round(v / reps, 4) for k, v in ms.items()}}
+
+
 def bench_served(M, torch, count: int = 400, seed: int = 5, load: float = 0.7):
     """Requests of log-uniform size in [2^10, 2^26] elements, uint32 or uint64,
     Poisson arrivals at `load` times the measured capacity; request r uses seed
@@ -215,7 +264,8 @@ def main():
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=29)
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched, served and listing-placement workloads")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched, served, listing-placement, records and small workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 2^28 uint32 (1 GiB) for counter calibration")
     args = ap.parse_args()
@@ -314,6 +364,10 @@ def main():
         out["served"] = bench_served(M, torch)
         torch.cuda.empty_cache()
         out["r1_placement"] = bench_r1(M, torch)
+        torch.cuda.empty_cache()
+        out["records"] = bench_records(M, torch)
+        torch.cuda.empty_cache()
+        out["small"] = bench_small(M, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_log2)
     print(json.dumps(out), flush=True)

@@ -77,8 +77,8 @@ typedef struct ms_config {
   uint32_t levels_per_pass; /* HBM merge levels fused into one pass over the array (each
                                workgroup runs a tile of the top level and, below it, the
                                windows of the lower levels that feed it); 0 = default (3;
-                               4 for 4-byte elements when there are at least 13 HBM levels
-                               and 3 does not divide them); clamped to 1..4; the passes
+                               4 when there are at least 13 HBM levels, for 4-byte elements
+                               only if 3 does not divide them); clamped to 1..4; the passes
                                split the levels as evenly as possible */
   uint32_t lds_levels_max;  /* cap on merge levels run in LDS by the leaf kernel; 0 = as many as fit */
   uint32_t flags;           /* MS_CFG_HBM_ONLY: run every merge level as an HBM pass;

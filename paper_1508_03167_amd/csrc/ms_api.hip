@@ -160,14 +160,15 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
     tiles = std::max<uint64_t>(tiles, (uint64_t)lv.nmerge * lv.tpm);
   }
   // fused passes: groups of at most lpp consecutive HBM levels, sizes within
-  // one; or one streaming pass and one patch kernel per level.  Default: 3;
-  // for 4-byte elements 4 when there are at least 13 HBM levels and 3 does
+  // one; or one streaming pass and one patch kernel per level.  Default: 3,
+  // and 4 at 13 or more HBM levels -- for 4-byte elements only when 3 does
   // not divide them (measured: a 4-level pass costs about as much per level
-  // as a 3-level one, and it pays to drop the 2-level passes a split by 3
-  // would leave; at fewer levels the 4-level tile's set-up does not pay)
+  // as a 3-level one, so fewer passes pay at the large sizes; for 4-byte
+  // elements an even split by 3 is as fast, and at fewer levels the 4-level
+  // tile's set-up does not pay)
   uint32_t lpp = 3u;
   if (cfg && cfg->levels_per_pass) lpp = cfg->levels_per_pass;
-  else if (eb == 4 && hp.nlev >= 13 && hp.nlev % 3 != 0) lpp = 4u;
+  else if (hp.nlev >= 13 && (eb != 4 || hp.nlev % 3 != 0)) lpp = 4u;
   if (lpp > (uint32_t)kGroupMax) lpp = kGroupMax;
   hp.fused = !(cfg && (cfg->flags & MS_CFG_ONE_LEVEL_PASSES)) && !r1;
   pa.placement = r1 ? 1u : 0u;
