@@ -432,10 +432,13 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t ntiles) {
   return x * q + min(x, r) + i;
 }
 
-// The 4-level tile is asked to fit 64 VGPRs (8 waves per SIMD, as its LDS
-// allows); the others fit by themselves.
+// The 4-level tile of 4-byte elements is asked to fit 64 VGPRs (8 waves per
+// SIMD, as its LDS allows); the others fit by themselves or are bound by LDS.
 template <typename E, int T, int LAM, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(LAM == 4 ? 8 : 1)))
+constexpr int kGroupWaves = LAM == 4 && sizeof(E) == 4 && NT == 512 ? 8 : 1;
+
+template <typename E, int T, int LAM, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kGroupWaves<E, T, LAM, NT>)))
 group_kernel(GroupArgs a) {
   if (blockIdx.x >= a.ntiles) return;
   group_body<E, T, LAM, NT>(a, xcd_tile(a.ntiles));
@@ -444,7 +447,8 @@ group_kernel(GroupArgs a) {
 // The same pass of many arrays in one launch: job j owns tiles
 // [tpre[j], tpre[j+1]) of the ntiles = tpre[njobs] tiles.
 template <typename E, int T, int LAM, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(LAM == 4 ? 8 : 1))) group_multi_kernel(const GroupArgs* __restrict__ jobs,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kGroupWaves<E, T, LAM, NT>)))
+group_multi_kernel(const GroupArgs* __restrict__ jobs,
                                                          const uint32_t* __restrict__ tpre, uint32_t njobs,
                                                          uint32_t ntiles) {
   if (blockIdx.x >= ntiles) return;
