@@ -144,6 +144,8 @@ typedef struct ms_plan_info {
   uint64_t leaves;        /* q = 2^c */
   uint64_t scratch_bytes; /* library scratch for this call (array copy + plan) */
   uint64_t pass_tiles;    /* workgroups of one HBM merge pass */
+  uint32_t hbm_passes;    /* passes over HBM that run the hbm_levels */
+  uint32_t max_levels_per_pass; /* merge levels of the largest such pass */
 } ms_plan_info;
 
 int ms_plan(uint64_t n, uint32_t elem_bytes, const ms_config* cfg, ms_plan_info* out);

@@ -37,7 +37,8 @@ class MSConfig(ctypes.Structure):
 class MSPlanInfo(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_uint32), ("lds_levels", ctypes.c_uint32), ("hbm_levels", ctypes.c_uint32),
                 ("leaf_B", ctypes.c_uint32), ("leaves", ctypes.c_uint64), ("scratch_bytes", ctypes.c_uint64),
-                ("pass_tiles", ctypes.c_uint64)]
+                ("pass_tiles", ctypes.c_uint64), ("hbm_passes", ctypes.c_uint32),
+                ("max_levels_per_pass", ctypes.c_uint32)]
 
 
 class MSError(RuntimeError):

@@ -853,6 +853,10 @@ int ms_plan(uint64_t n, uint32_t elem_bytes, const ms_config* cfg, ms_plan_info*
   out->leaves = hp.q;
   out->scratch_bytes = scratch_of(hp);
   out->pass_tiles = hp.pass_tiles;
+  out->hbm_passes = hp.fused ? hp.ngroup : hp.nlev;
+  out->max_levels_per_pass = hp.nlev ? 1u : 0u;
+  for (uint32_t g = 0; hp.fused && g < hp.ngroup; ++g)
+    out->max_levels_per_pass = std::max(out->max_levels_per_pass, hp.glam[g]);
   return MS_OK;
 }
 

@@ -47,6 +47,31 @@ def test_plan_matches_the_driver_partition():
     assert p["lds_levels"] == 0 and p["levels"] == p["hbm_levels"]
 
 
+def test_levels_per_pass_default_and_knob():
+    # default: 3 levels per pass, 4 from 13 HBM levels on (for 4-byte
+    # elements only when 3 does not divide them); the passes split the
+    # levels as evenly as possible
+    M, _ = _lib()
+    for k in range(17, 33):
+        n = min(1 << k, (1 << 32) - (1 << 17))
+        for eb in (4, 8, 16):
+            p = M.plan(n, eb)
+            h = p["hbm_levels"]
+            lpp = 4 if h >= 13 and (eb != 4 or h % 3) else 3
+            passes = -(-h // lpp)
+            assert p["hbm_passes"] == passes, (k, eb, p)
+            assert p["max_levels_per_pass"] == (-(-h // passes) if h else 0), (k, eb, p)
+    p = M.plan(1 << 30)
+    assert (p["hbm_levels"], p["hbm_passes"], p["max_levels_per_pass"]) == (16, 4, 4)
+    p = M.plan(1 << 26)
+    assert (p["hbm_levels"], p["hbm_passes"], p["max_levels_per_pass"]) == (12, 4, 3)
+    for lpp in (1, 2, 3, 4, 9):
+        p = M.plan(1 << 30, levels_per_pass=lpp)
+        assert p["hbm_passes"] == -(-16 // min(lpp, 4))
+    p = M.plan(1 << 30, one_level_passes=True)
+    assert p["hbm_passes"] == 16 and p["max_levels_per_pass"] == 1
+
+
 def test_rejects_bad_arguments_without_a_device():
     M, L = _lib()
     assert L.ms_shuffle(None, 10, 4, 1, None) == -1          # null pointer, n > 0
