@@ -432,10 +432,11 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t ntiles) {
   return x * q + min(x, r) + i;
 }
 
-// The 4-level tile of 4-byte elements is asked to fit 64 VGPRs (8 waves per
-// SIMD, as its LDS allows); the others fit by themselves or are bound by LDS.
+// The 4-level tiles of 4- and 8-byte elements are asked to fit 64 VGPRs (8
+// waves per SIMD, as their LDS allows); the others fit by themselves or are
+// bound by their VGPRs.
 template <typename E, int T, int LAM, int NT>
-constexpr int kGroupWaves = LAM == 4 && sizeof(E) == 4 && NT == 512 ? 8 : 1;
+constexpr int kGroupWaves = LAM == 4 && sizeof(E) <= 8 && NT == 512 ? 8 : 1;
 
 template <typename E, int T, int LAM, int NT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kGroupWaves<E, T, LAM, NT>)))
@@ -464,7 +465,10 @@ group_multi_kernel(const GroupArgs* __restrict__ jobs,
 
 // Slots per tile for 4-byte elements: 4096 with 512 threads (the default:
 // measured faster) or 2048 with 256 threads (MS_GROUP_TILE=2048).  A tuning
-// knob only: the permutation does not depend on it.
+// knob only: the permutation does not depend on it.  8-byte elements take
+// 2048 slots with 512 threads (8 waves per SIMD; measured faster than 256),
+// 16-byte elements 1024 slots with 256 threads (512 measured much slower:
+// at 78-94 VGPRs the larger workgroup fits fewer times per CU).
 static int group_tile_u32() {
   static const int t = [] {
     const char* e = getenv("MS_GROUP_TILE");
@@ -501,7 +505,7 @@ void launch_group_multi(const GroupArgs* jobs, const uint32_t* tpre, uint32_t nj
     if (group_tile_u32() == 2048) launch_group_multi_t<uint32_t, 2048, 256>(jobs, tpre, njobs, ntiles, lam, st);
     else launch_group_multi_t<uint32_t, 4096, 512>(jobs, tpre, njobs, ntiles, lam, st);
   } else if (eb == 8) {
-    launch_group_multi_t<uint64_t, 2048, 256>(jobs, tpre, njobs, ntiles, lam, st);
+    launch_group_multi_t<uint64_t, 2048, 512>(jobs, tpre, njobs, ntiles, lam, st);
   } else {
     launch_group_multi_t<uint4, 1024, 256>(jobs, tpre, njobs, ntiles, lam, st);
   }
@@ -512,7 +516,7 @@ void launch_group(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipSt
     if (group_tile_u32() == 2048) launch_group_t<uint32_t, 2048, 256>(a, lam, grid, st);
     else launch_group_t<uint32_t, 4096, 512>(a, lam, grid, st);
   } else if (eb == 8) {
-    launch_group_t<uint64_t, 2048, 256>(a, lam, grid, st);
+    launch_group_t<uint64_t, 2048, 512>(a, lam, grid, st);
   } else {
     launch_group_t<uint4, 1024, 256>(a, lam, grid, st);
   }
