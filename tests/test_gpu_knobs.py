@@ -1,7 +1,9 @@
 """GPU parity under the library's tuning knobs, each read once per process
 (so each runs in a child process): the 1024-thread leaf with 128 KiB
-super-blocks (MS_LEAF_BIG=1) and 2048-slot fused-pass tiles
-(MS_GROUP_TILE=2048).  The permutation must not depend on either."""
+super-blocks (MS_LEAF_BIG=1), 2048-slot fused-pass tiles
+(MS_GROUP_TILE=2048) and the one-level pass's other tile sizes and staging
+modes (MS_PASS_VARIANT=1..5, with one-level passes).  The permutation must
+not depend on any of them."""
 import os
 import subprocess
 import sys
@@ -18,18 +20,19 @@ sys.path.insert(0, %r)
 import numpy as np, torch
 import paper_1508_03167_amd as M
 from oracle import oracle as O
+KW = %r
 for n, seed, eb in [(70001, 3, 4), ((1 << 20) + 3, 4, 4), (3_000_017, 5, 4), (300_007, 6, 8), (123_457, 7, 16)]:
     want, wbits = O.permutation(n, 4096, seed)
     bits = torch.zeros(1, dtype=torch.int64, device="cuda")
     if eb == 4:
         x = torch.empty(n, dtype=torch.int32, device="cuda")
-        M.permutation(x, seed, bits=bits)
+        M.permutation(x, seed, bits=bits, **KW)
         got = x.cpu().numpy().view(np.uint32)
         ok = np.array_equal(got, want)
     else:
         host = np.random.default_rng(eb).integers(0, 2**63, size=(n, eb // 8), dtype=np.int64)
         x = torch.from_numpy(host.copy()).cuda()
-        M.shuffle_(x, seed, bits=bits)
+        M.shuffle_(x, seed, bits=bits, **KW)
         ok = np.array_equal(x.cpu().numpy(), host[want.astype(np.int64)])
     torch.cuda.synchronize()
     status = M.device_status()
@@ -37,11 +40,15 @@ for n, seed, eb in [(70001, 3, 4), ((1 << 20) + 3, 4, 4), (3_000_017, 5, 4), (30
 """
 
 
-@pytest.mark.parametrize("knob", [{"MS_LEAF_BIG": "1"}, {"MS_GROUP_TILE": "2048"}])
-def test_tuning_knob_keeps_the_permutation(knob):
-    print(f"[gpu] knob {knob}", flush=True)
+KNOBS = [({"MS_LEAF_BIG": "1"}, {}), ({"MS_GROUP_TILE": "2048"}, {})] + [
+    ({"MS_PASS_VARIANT": str(v)}, {"one_level_passes": True}) for v in range(1, 6)]
+
+
+@pytest.mark.parametrize("knob,kw", KNOBS)
+def test_tuning_knob_keeps_the_permutation(knob, kw):
+    print(f"[gpu] knob {knob} {kw}", flush=True)
     env = dict(os.environ, **knob)
-    r = subprocess.run([sys.executable, "-c", CHILD % os.path.dirname(HERE)], env=env, capture_output=True,
+    r = subprocess.run([sys.executable, "-c", CHILD % (os.path.dirname(HERE), kw)], env=env, capture_output=True,
                        text=True, timeout=300)
     lines = [l for l in r.stdout.splitlines() if l.startswith("case")]
     assert r.returncode == 0 and len(lines) == 5, (r.stdout, r.stderr[-2000:])
