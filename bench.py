@@ -56,6 +56,19 @@ def traffic_from_profiles(kernel: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def valu_issue_from_profiles(kernel_class: str):
+    """Fraction of the chip's VALU issue capacity the kernel used, from the
+    committed instruction-counter summary, if it was taken on the current
+    kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "merge_pass_and_leaf_n2^30_u32_instructions.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_hash") != kernel_source_hash() or kernel_class not in d:
+        return None
+    return round(d[kernel_class]["valu_issue_frac"], 3)
+
+
 def cpu_baseline(n_log2: int):
     from oracle import oracle as O
 
@@ -317,7 +330,8 @@ def main():
                 "kernel": "group_kernel<uint32_t,4096,levels>", "avg_launch_ms": round(avg, 4),
                 "launches": cnt_cls["merge_pass"],
                 "levels_per_launch": round(plan["hbm_levels"] * args.steps / launches, 3),
-                "alg_bytes_per_launch": 2 * n * 4}
+                "alg_bytes_per_launch": 2 * n * 4,
+                "valu_issue_frac_from_counters": valu_issue_from_profiles("merge_pass")}
 
     def leaf_roof():
         launches = max(cnt_cls["leaf"], 1)
@@ -328,7 +342,8 @@ def main():
                 "frac": round(ach / ALU_PEAK_GOPS, 4), "traffic": traffic_from_profiles("leaf_n2^30_u32"),
                 "kernel": "leaf_kernel<uint32_t,16384,512>", "avg_launch_ms": round(avg, 4),
                 "launches": cnt_cls["leaf"], "alg_ops_per_launch": ops_per_elem * n,
-                "alg_bytes_per_launch": 2 * n * 4}
+                "alg_bytes_per_launch": 2 * n * 4,
+                "valu_issue_frac_from_counters": valu_issue_from_profiles("leaf")}
 
     roofs = {"merge_pass": pass_roof(), "leaf": leaf_roof()}
     dominant = max(("merge_pass", "leaf"), key=lambda k: ms_cls[k])
