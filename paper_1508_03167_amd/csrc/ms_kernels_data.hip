@@ -590,13 +590,16 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
           const uint32_t bp = t0 & 31;
           const uint32_t r0 = maux.wpre[w] - maux.wpre[mm * W] + (uint32_t)__popc(~wlo & ((1u << bp) - 1u));
           const uint32_t bits4 = (uint32_t)((((uint64_t)whi << 32) | wlo) >> bp);
-          const uint32_t ab = m0 + r0, bb = m0 + n1 + t0 - r0;
-          uint32_t o = 0;
+          // xb = B's next source and xa + j = A's, moved by the all-ones mask
+          // of each 1 flip (kept opaque: a bit select, not compare and select)
+          uint32_t xa = m0 + r0, xb = m0 + n1 + t0 - r0;
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const uint32_t bit = (bits4 >> j) & 1u;
-            src[j] = bit ? bb + o : ab + j - o;
-            o += bit;
+            uint32_t m = 0u - ((bits4 >> j) & 1u);
+            asm volatile("" : "+v"(m));
+            src[j] = (xb & m) | ((xa + j) & ~m);
+            xb -= m;
+            xa += m;
           }
         } else {
 #pragma unroll

@@ -348,15 +348,18 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, uint32_t tile) {
         // four slots of the window before the break step: with o_j the ones
         // among the first j flips, slot j takes B at bb + o_j or A at
         // ab + j - o_j
-        uint32_t ab = h1.x + z0, bb = h1.y + t0 - z0;
-        // one value each (kept from being re-expanded per slot)
-        asm volatile("" : "+v"(ab), "+v"(bb));
-        uint32_t o = 0;
+        // x = bb + o_j and w = ab - o_j, moved by the all-ones mask of each
+        // 1 flip; the slot picks x or w + j through that mask (kept opaque so
+        // that it stays a bit select instead of a compare and a select)
+        uint32_t w = h1.x + z0, x = h1.y + t0 - z0;
+        asm volatile("" : "+v"(w), "+v"(x));
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const uint32_t bit = (bits4 >> j) & 1u;
-          fr[j] = bit ? bb + o : ab + j - o;
-          o += bit;
+          uint32_t m = 0u - ((bits4 >> j) & 1u);
+          asm volatile("" : "+v"(m));
+          fr[j] = (x & m) | ((w + j) & ~m);
+          x -= m;
+          w += m;
         }
       } else {
         const uint32_t P = win[k].P;
