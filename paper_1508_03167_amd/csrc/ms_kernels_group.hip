@@ -298,12 +298,15 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, uint32_t tile) {
       if (pm[PK + i] != NONE) pv[PK + i] = XR[src];
     }
   }
-  // per window, what the interleave needs: slot t = s + toff for LDS slot s;
-  // before the break step, a zero flip takes A[z] (at off + z) and a one
-  // takes B[t - u0 - z] (at bdelta + t - z), z = zeros in [u0, t) = the
-  // wpre-based count minus zbase; from the break step on, t maps to t + pdelta.
-  // lim = min(u1, P): a group of 4 slots below it takes the short path.
-  // gpre: groups of 4 slots in the windows before it on its level.
+  // per window, what the interleave needs.  Group q of the level (4 slots)
+  // lies in window k from gpre = the groups of the windows before it on its
+  // level; its LDS slot is s0 = off + 4 (q - gpre) and its merge slot
+  // t0 = u0 + 4 (q - gpre), both one multiply-add from 4q.  Before the break
+  // step, with zp = the wpre-based zero count before slot t (zeros in
+  // [u0, t) plus zbase), a zero flip takes A at off + zp - zbase and a one
+  // takes B at (off + la4 - u0 + zbase) + t - zp; from the break step on, t
+  // maps to t + pdelta.  lim = min(u1, P): a group of 4 slots below it takes
+  // the short path.
   if (tid < NODES) {
     const Win& w = win[tid];
     const int d = 31 - __clz(tid + 1);
@@ -315,8 +318,9 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, uint32_t tile) {
     const uint32_t pdelta = w.side == 0 ? w.off + la4 - w.n1 - w.u0 + w.ra0 : w.off - w.n2 - w.ra0;
     uint32_t gpre = 0;
     for (int q = (1 << d) - 1; q < tid; ++q) gpre += (win[q].u1 - win[q].u0 + 3u) >> 2;
-    *reinterpret_cast<uint4*>(&hot[tid][0]) = make_uint4(w.u0 - w.off, min(w.u1, w.P), wbase, zbase);
-    *reinterpret_cast<uint4*>(&hot[tid][4]) = make_uint4(w.off, w.off + la4 - w.u0, pdelta, gpre);
+    *reinterpret_cast<uint4*>(&hot[tid][0]) = make_uint4(w.u0 - 4 * gpre, min(w.u1, w.P), wbase, w.off - zbase);
+    *reinterpret_cast<uint4*>(&hot[tid][4]) =
+        make_uint4(w.off - 4 * gpre, w.off + la4 - w.u0 + zbase, pdelta, gpre);
     if (tid == (2 << d) - 2) lgroups[LAM - 1 - d] = gpre + ((w.u1 - w.u0 + 3u) >> 2);
   }
   __syncthreads();
@@ -337,11 +341,11 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, uint32_t tile) {
       for (int q = 1; q < (1 << d); ++q) k += g >= hot[kf + q][7] ? 1 : 0;
       const uint4 h0 = *reinterpret_cast<const uint4*>(&hot[k][0]);
       const uint4 h1 = *reinterpret_cast<const uint4*>(&hot[k][4]);
-      const uint32_t s0 = h1.x + 4 * (g - h1.w);
-      const uint32_t t0 = s0 + h0.x;
+      const uint32_t s0 = 4 * g + h1.x;
+      const uint32_t t0 = 4 * g + h0.x;
       const uint32_t wi = min(h0.z + (t0 >> 5), (uint32_t)NWORD - 2);
       const uint32_t wlo = words[wi], whi = words[wi + 1];
-      const uint32_t z0 = wpre[wi] - h0.w + (uint32_t)__popc(~wlo & ((1u << (t0 & 31)) - 1u));
+      const uint32_t zp = wpre[wi] + (uint32_t)__popc(~wlo & ((1u << (t0 & 31)) - 1u));
       const uint32_t bits4 = (uint32_t)((((uint64_t)whi << 32) | wlo) >> (t0 & 31));
       uint32_t fr[4];
       if (t0 + 4 <= h0.y) {
@@ -351,7 +355,7 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, uint32_t tile) {
         // x = bb + o_j and w = ab - o_j, moved by the all-ones mask of each
         // 1 flip; the slot picks x or w + j through that mask (kept opaque so
         // that it stays a bit select instead of a compare and a select)
-        uint32_t w = h1.x + z0, x = h1.y + t0 - z0;
+        uint32_t w = h0.w + zp, x = h1.y + t0 - zp;
         asm volatile("" : "+v"(w), "+v"(x));
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -363,12 +367,12 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, uint32_t tile) {
         }
       } else {
         const uint32_t P = win[k].P;
-        uint32_t z = z0;
+        uint32_t z = zp;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const uint32_t t = t0 + j;
           const uint32_t bit = (bits4 >> j) & 1u;
-          const uint32_t rk = bit ? h1.y + t - z : h1.x + z;
+          const uint32_t rk = bit ? h1.y + t - z : h0.w + z;
           fr[j] = min(t < P ? rk : t + h1.z, (uint32_t)TB - 1);
           z += bit ^ 1u;
         }
