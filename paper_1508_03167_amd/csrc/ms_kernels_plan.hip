@@ -71,9 +71,10 @@ __device__ __forceinline__ MergeGeom merge_geom(const PlanArgs& pa, uint32_t L, 
 __device__ __forceinline__ void plan_count_body(const PlanArgs& pa, uint64_t chunk, uint32_t* tmp) {
   const int l = level_of_chunk(pa, chunk);
   const HbmLevel& lv = pa.lev[l];
-  const uint64_t rel = chunk - lv.chunk_base;
-  const uint32_t m = (uint32_t)(rel / lv.cpm);
-  const uint32_t ch = (uint32_t)(rel % lv.cpm);
+  // chunks of one level number fewer than 2^32: a 32-bit division
+  const uint32_t rel = (uint32_t)(chunk - lv.chunk_base);
+  const uint32_t m = rel / lv.cpm;
+  const uint32_t ch = rel - m * lv.cpm;
   const Key key{pa.key0, pa.key1};
   const uint32_t g = (ch << kChunkGranLog) + threadIdx.x;
   const W4 f = flip_block(g, m, lv.L, key);
@@ -131,7 +132,7 @@ __device__ __forceinline__ void zc_body(const PlanArgs& pa, uint64_t c) {
   }
   if (c >= pa.total_chunks) return;
   const HbmLevel& lv = pa.lev[level_of_chunk(pa, c)];
-  const uint64_t first = c - (c - lv.chunk_base) % lv.cpm;
+  const uint64_t first = c - (uint32_t)(c - lv.chunk_base) % lv.cpm;
   pa.zc[c] = pa.zg[c] - pa.zg[first];
 }
 __global__ void __launch_bounds__(256) zc_kernel(PlanArgs pa) { zc_body(pa, (uint64_t)blockIdx.x * 256 + threadIdx.x); }
@@ -207,9 +208,10 @@ __device__ __forceinline__ TailWg tail_wg(const PlanArgs& pa, uint64_t wg) {
   const int l = level_of_wg(pa, wg);
   t.l = l;
   t.lv = &pa.lev[l];
-  const uint64_t rel = wg - t.lv->wg_base;
-  t.m = (uint32_t)(rel / t.lv->wpm);
-  t.w = (uint32_t)(rel % t.lv->wpm);
+  // workgroups of one level number fewer than 2^32: a 32-bit division
+  const uint32_t rel = (uint32_t)(wg - t.lv->wg_base);
+  t.m = rel / t.lv->wpm;
+  t.w = rel - t.m * t.lv->wpm;
   t.g = merge_geom(pa, t.lv->L, t.m);
   t.gm = t.lv->merge_base + t.m;
   t.P = pa.P[t.gm];
