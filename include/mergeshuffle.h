@@ -87,7 +87,7 @@ typedef struct ms_config {
                                is then ignored);
                                MS_CFG_PLACEMENT_R1: place the elements of each merge's
                                coin-flip loop as the printed Merge listing's in-place swaps do
-                               (Section 4 listing; the default places them by the stable
+                               (Appendix A.1 merge() listing; the default places them by the stable
                                interleave).  The same bits, break steps and draws are used and
                                the same B elements land on the same slots; only the order of
                                the A elements differs.  Every level then runs as a one-level

@@ -29,14 +29,15 @@ void launch_plan(const PlanArgs& pa, hipStream_t st);
 void launch_plan_multi(const PlanArgs* pas, uint32_t njobs, const uint32_t* const* pre, const uint32_t* units,
                        hipStream_t st);
 void launch_leaf_multi(const LeafArgs* jobs, const uint32_t* wpre, uint32_t njobs, uint32_t nwg, uint32_t eb,
-                       hipStream_t st);
+                       bool big, hipStream_t st);
 void launch_group_multi(const GroupArgs* jobs, const uint32_t* tpre, uint32_t njobs, uint32_t ntiles, int lam,
                         uint32_t eb, hipStream_t st);
-void launch_leaf(const LeafArgs& a, uint32_t eb, bool ident, uint64_t grid, hipStream_t st);
+void launch_leaf(const LeafArgs& a, uint32_t eb, bool ident, bool big, uint64_t grid, hipStream_t st);
 void launch_merge_pass(const PassArgs& a, uint32_t eb, uint64_t grid, hipStream_t st);
 void launch_patch(const PlanArgs& pa, int l, const void* in, void* out, uint32_t eb, hipStream_t st);
 void launch_merge_r1(const PlanArgs& pa, int l, const void* in, void* out, uint32_t eb, hipStream_t st);
-int leaf_capacity(uint32_t eb);
+int leaf_capacity(uint32_t eb, bool big);
+bool leaf_big_default();
 int leaf_max_block();
 int leaf_max_levels();
 int pass_tile(uint32_t eb);
@@ -82,6 +83,7 @@ struct HostPlan {
   uint64_t q = 1;
   uint64_t pass_tiles = 0;
   bool fused = true;              // HBM levels run as fused groups (else one pass + patch per level)
+  bool leaf_big = false;          // 128 KiB leaf super-block (1024 threads)
   uint32_t ngroup = 0;
   uint32_t gfirst[kMaxLevels];    // first HBM level index of each group
   uint32_t glam[kMaxLevels];      // levels in each group
@@ -107,7 +109,10 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
   while ((n >> c) > B) ++c;
   hp.c = c;
   hp.q = 1ull << c;
-  const uint64_t scap = (uint64_t)leaf_capacity(eb);
+  // the default super-block, or the 128 KiB one when a leaf does not fit
+  // (16-byte leaves of cutoff + 1 = 4097 records)
+  hp.leaf_big = leaf_big_default() || ceil_shift(n, c) > (uint64_t)leaf_capacity(eb, false);
+  const uint64_t scap = (uint64_t)leaf_capacity(eb, hp.leaf_big);
   if (ceil_shift(n, c) > scap) return fail(MS_ERR_UNSUPPORTED, "leaf of %llu elements does not fit in LDS",
                                            (unsigned long long)ceil_shift(n, c));
   uint32_t lam_max = (uint32_t)leaf_max_levels();
@@ -332,7 +337,7 @@ struct ProfScope {
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(int c, hipStream_t s) : cls(c), st(s) {
-    if (!g_prof) return;
+    if (!g_prof || c < 0) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
     (void)hipEventRecord(a, st);
   }
@@ -407,54 +412,38 @@ GroupArgs group_args(const HostPlan& hp, uint32_t g, const void* cur, void* othe
   return ga;
 }
 
-int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, const ms_config* cfg,
-            unsigned long long* d_bits, bool ident) {
-  HostPlan hp;
-  int rc = make_plan(n, eb, cfg, hp);
-  if (rc) return rc;
-  if (n > 0 && ptr == nullptr) return fail(MS_ERR_INVALID, "null pointer with n = %llu", (unsigned long long)n);
-  if (((uintptr_t)ptr) % eb != 0) return fail(MS_ERR_INVALID, "pointer not aligned to %u bytes", eb);
-  if (n <= 1) return MS_OK;
-  DeviceCtx* dc;
-  Arena* arp;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    if ((rc = device_ctx(&dc))) return rc;
-    arp = &dc->arenas[st];  // map nodes do not move
-  }
-  // the stream's scratch is this call's until its launches are queued
-  std::lock_guard<std::mutex> alk(arp->mu);
-  Arena& ar = *arp;
-  if ((rc = ensure(&ar.data, &ar.data_bytes, hp.nlev ? n * eb : 0, st))) return rc;
-  if ((rc = ensure(&ar.plan, &ar.plan_bytes, hp.lay.bytes, st))) return rc;
-  unsigned long long* bits = d_bits ? d_bits : dc->dummy_bits;
+// The launch sequence of one call: the plan (on plan_st, forked from and
+// joined back into st by the two events, or on st itself when plan_st is
+// null), the leaf kernel and the HBM passes, alternating between the
+// caller's array X and the scratch copy Y so that the last pass lands in X.
+// plan_area holds hp.lay.bytes bytes.  `prof` brackets the launches with
+// timing events when profiling is on.
+int enqueue_call(HostPlan& hp, void* X, void* Y, void* plan_area, uint64_t seed, hipStream_t st,
+                 hipStream_t plan_st, hipEvent_t plan_fork, hipEvent_t plan_join, unsigned long long* bits,
+                 uint32_t* status, bool ident, bool prof) {
+  const uint64_t n = hp.n;
+  const uint32_t eb = hp.eb;
   PlanArgs& pa = hp.pa;
   pa.key0 = (uint32_t)seed;
   pa.key1 = (uint32_t)(seed >> 32);
   pa.bits = bits;
-  pa.status = dc->status;
-  bool plan_forked = false;
+  pa.status = status;
+  const bool fork = hp.nlev && plan_st;
   if (hp.nlev) {
-    bind_plan(hp, ar.plan);
+    bind_plan(hp, plan_area);
     // the plan depends only on (n, cutoff, seed), the leaf kernel only on
-    // the data: the plan goes to the arena's plan stream and the first HBM
-    // pass waits for it
-    if (!ar.plan_st) {
-      HIP_TRY(hipStreamCreateWithFlags(&ar.plan_st, hipStreamNonBlocking));
-      HIP_TRY(hipEventCreateWithFlags(&ar.plan_fork, hipEventDisableTiming));
-      HIP_TRY(hipEventCreateWithFlags(&ar.plan_join, hipEventDisableTiming));
+    // the data: with a plan stream the plan runs beside the leaf kernel and
+    // the first HBM pass waits for it
+    if (fork) {
+      HIP_TRY(hipEventRecord(plan_fork, st));
+      HIP_TRY(hipStreamWaitEvent(plan_st, plan_fork, 0));
     }
-    HIP_TRY(hipEventRecord(ar.plan_fork, st));
-    HIP_TRY(hipStreamWaitEvent(ar.plan_st, ar.plan_fork, 0));
     {
-      ProfScope ps(0, ar.plan_st);
-      launch_plan(pa, ar.plan_st);
+      ProfScope ps(prof ? 0 : -1, fork ? plan_st : st);
+      launch_plan(pa, fork ? plan_st : st);
     }
-    HIP_TRY(hipEventRecord(ar.plan_join, ar.plan_st));
-    plan_forked = true;
+    if (fork) HIP_TRY(hipEventRecord(plan_join, plan_st));
   }
-  void* X = ptr;
-  void* Y = ar.data;
   const uint32_t npass = hp.fused ? hp.ngroup : hp.nlev;
   void* cur = (npass % 2 == 0) ? X : Y;
   {
@@ -467,18 +456,18 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
     la.key0 = pa.key0;
     la.key1 = pa.key1;
     la.bits = bits;
-    la.status = dc->status;
-    ProfScope ps(1, st);
-    launch_leaf(la, eb, ident, hp.q >> hp.lam, st);
+    la.status = status;
+    ProfScope ps(prof ? 1 : -1, st);
+    launch_leaf(la, eb, ident, hp.leaf_big, hp.q >> hp.lam, st);
   }
-  if (plan_forked) HIP_TRY(hipStreamWaitEvent(st, ar.plan_join, 0));
+  if (fork) HIP_TRY(hipStreamWaitEvent(st, plan_join, 0));
   for (uint32_t g = 0; hp.fused && g < hp.ngroup; ++g) {
     void* other = cur == X ? Y : X;
     const GroupInfo& gi = pa.grp[g];
     const GroupArgs ga = group_args(hp, g, cur, other);
     const HbmLevel& top = pa.lev[gi.lf + gi.lam - 1];
     {
-      ProfScope ps(2, st);
+      ProfScope ps(prof ? 2 : -1, st);
       launch_group(ga, (int)gi.lam, eb, (uint64_t)top.nmerge * gi.tpm, st);
     }
     cur = other;
@@ -504,12 +493,12 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
     a.key1 = pa.key1;
     a.vec_ok = ((uintptr_t)cur % 16 == 0) ? 1u : 0u;
     {
-      ProfScope ps(2, st);
+      ProfScope ps(prof ? 2 : -1, st);
       if (pa.placement) launch_merge_r1(pa, (int)l, cur, other, eb, st);
       else launch_merge_pass(a, eb, (uint64_t)lv.nmerge * lv.tpm, st);
     }
     {
-      ProfScope ps(3, st);
+      ProfScope ps(prof ? 3 : -1, st);
       launch_patch(pa, (int)l, cur, other, eb, st);
     }
     cur = other;
@@ -517,6 +506,40 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(MS_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
   return MS_OK;
+}
+
+int check_args(const HostPlan& hp, const void* ptr) {
+  if (hp.n > 0 && ptr == nullptr) return fail(MS_ERR_INVALID, "null pointer with n = %llu", (unsigned long long)hp.n);
+  if (((uintptr_t)ptr) % hp.eb != 0) return fail(MS_ERR_INVALID, "pointer not aligned to %u bytes", hp.eb);
+  return MS_OK;
+}
+
+int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, const ms_config* cfg,
+            unsigned long long* d_bits, bool ident) {
+  HostPlan hp;
+  int rc = make_plan(n, eb, cfg, hp);
+  if (rc) return rc;
+  if ((rc = check_args(hp, ptr))) return rc;
+  if (n <= 1) return MS_OK;
+  DeviceCtx* dc;
+  Arena* arp;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if ((rc = device_ctx(&dc))) return rc;
+    arp = &dc->arenas[st];  // map nodes do not move
+  }
+  // the stream's scratch is this call's until its launches are queued
+  std::lock_guard<std::mutex> alk(arp->mu);
+  Arena& ar = *arp;
+  if ((rc = ensure(&ar.data, &ar.data_bytes, hp.nlev ? n * eb : 0, st))) return rc;
+  if ((rc = ensure(&ar.plan, &ar.plan_bytes, hp.lay.bytes, st))) return rc;
+  if (hp.nlev && !ar.plan_st) {
+    HIP_TRY(hipStreamCreateWithFlags(&ar.plan_st, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&ar.plan_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&ar.plan_join, hipEventDisableTiming));
+  }
+  return enqueue_call(hp, ptr, ar.data, ar.plan, seed, st, ar.plan_st, ar.plan_fork, ar.plan_join,
+                      d_bits ? d_bits : dc->dummy_bits, dc->status, ident, true);
 }
 
 // The arrays of a batched call with at most kWaveMaxN elements run in
@@ -575,6 +598,9 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
   const size_t head = offsetof(PlanArgs, lev);
   const uint32_t wmax = wave_max_arrays();
   auto cls_of = [](uint32_t eb) { return eb == 4 ? 0u : eb == 8 ? 1u : 2u; };
+  // leaf launch classes: element size x super-block size
+  constexpr int kLeafCls = 6;
+  auto leaf_cls = [&](const HostPlan& hp) { return cls_of(hp.eb) * 2 + (hp.leaf_big ? 1u : 0u); };
   size_t i0 = 0;
   while (i0 < idx.size()) {
     // the wave: arrays idx[i0 .. i1)
@@ -589,12 +615,12 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
     const uint32_t nw = (uint32_t)(i1 - i0);
     // launch classes: plan jobs (arrays with HBM passes), leaves per element
     // size, fused pass g per (g, element size, levels)
-    uint32_t np = 0, nleaf[3] = {0, 0, 0};
+    uint32_t np = 0, nleaf[kLeafCls] = {0, 0, 0, 0, 0, 0};
     std::map<uint32_t, uint32_t> gcount;  // key (g * 3 + cls) * 4 + lam - 1, ordered by pass
     for (size_t i = i0; i < i1; ++i) {
       const HostPlan& hp = hps[i];
       const uint32_t cls = cls_of(hp.eb);
-      ++nleaf[cls];
+      ++nleaf[leaf_cls(hp)];
       if (hp.nlev) ++np;
       for (uint32_t g = 0; g < hp.ngroup; ++g) ++gcount[(g * 3 + cls) * 4 + hp.glam[g] - 1];
     }
@@ -607,8 +633,8 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
       pre_off[k] = o;
       o += align256(((size_t)np + 1) * 4);
     }
-    size_t leaf_off[3], wpre_off[3];
-    for (int c = 0; c < 3; ++c) {
+    size_t leaf_off[kLeafCls], wpre_off[kLeafCls];
+    for (int c = 0; c < kLeafCls; ++c) {
       leaf_off[c] = o;
       o += align256((size_t)nleaf[c] * sizeof(LeafArgs));
       wpre_off[c] = o;
@@ -650,7 +676,7 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
     char* h = reinterpret_cast<char*>(stg);
     char* d = reinterpret_cast<char*>(ar.wave);
     uint32_t pfill = 0, units[kUnits] = {0, 0, 0, 0, 0};
-    uint32_t lfill[3] = {0, 0, 0}, lwg[3] = {0, 0, 0};
+    uint32_t lfill[kLeafCls] = {0, 0, 0, 0, 0, 0}, lwg[kLeafCls] = {0, 0, 0, 0, 0, 0};
     for (uint32_t j = 0; j < nw; ++j) {
       HostPlan& hp = hps[i0 + j];
       const uint32_t a = idx[i0 + j];
@@ -691,10 +717,11 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
       la.key1 = pa.key1;
       la.bits = bits;
       la.status = dc->status;
-      memcpy(h + leaf_off[cls] + (size_t)lfill[cls] * sizeof(LeafArgs), &la, sizeof la);
-      reinterpret_cast<uint32_t*>(h + wpre_off[cls])[lfill[cls]] = lwg[cls];
-      ++lfill[cls];
-      lwg[cls] += (uint32_t)(hp.q >> hp.lam);
+      const uint32_t lc = leaf_cls(hp);
+      memcpy(h + leaf_off[lc] + (size_t)lfill[lc] * sizeof(LeafArgs), &la, sizeof la);
+      reinterpret_cast<uint32_t*>(h + wpre_off[lc])[lfill[lc]] = lwg[lc];
+      ++lfill[lc];
+      lwg[lc] += (uint32_t)(hp.q >> hp.lam);
       for (uint32_t g = 0; g < hp.ngroup; ++g) {
         void* other = cur == X ? Y : X;
         const GroupArgs ga = group_args(hp, g, cur, other);
@@ -707,7 +734,7 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
       }
     }
     for (int k = 0; k < kUnits; ++k) reinterpret_cast<uint32_t*>(h + pre_off[k])[np] = units[k];
-    for (int c = 0; c < 3; ++c) reinterpret_cast<uint32_t*>(h + wpre_off[c])[nleaf[c]] = lwg[c];
+    for (int c = 0; c < kLeafCls; ++c) reinterpret_cast<uint32_t*>(h + wpre_off[c])[nleaf[c]] = lwg[c];
     for (auto& kv : gsec) reinterpret_cast<uint32_t*>(h + kv.second.tpre_off)[kv.second.n] = kv.second.tiles;
     HIP_TRY(hipMemcpyAsync(d, h, desc_bytes, hipMemcpyHostToDevice, st));
     HIP_TRY(hipEventRecord(ar.stage_done[si], st));
@@ -717,12 +744,12 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
       ProfScope ps(0, st);
       launch_plan_multi(reinterpret_cast<const PlanArgs*>(d + pa_off), np, pre, units, st);
     }
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < kLeafCls; ++c) {
       if (!nleaf[c]) continue;
       ProfScope ps(1, st);
       launch_leaf_multi(reinterpret_cast<const LeafArgs*>(d + leaf_off[c]),
                         reinterpret_cast<const uint32_t*>(d + wpre_off[c]), nleaf[c], lwg[c],
-                        c == 0 ? 4u : c == 1 ? 8u : 16u, st);
+                        c / 2 == 0 ? 4u : c / 2 == 1 ? 8u : 16u, (c & 1) != 0, st);
     }
     for (auto& kv : gsec) {
       const uint32_t key = kv.first;

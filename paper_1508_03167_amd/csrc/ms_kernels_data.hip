@@ -53,20 +53,6 @@ struct MergeAux {
   uint32_t wpre[kWords];
 };
 
-// Swap a 16-bit entry of a packed LDS array (two entries per 32-bit word);
-// returns the old entry.
-__device__ __forceinline__ uint32_t xchg_u16(uint16_t* arr, uint32_t pos, uint32_t val) {
-  uint32_t* w = reinterpret_cast<uint32_t*>(arr) + (pos >> 1);
-  const uint32_t sh = (pos & 1u) * 16u;
-  uint32_t cur = *w;
-  for (;;) {
-    const uint32_t nv = (cur & ~(0xFFFFu << sh)) | (val << sh);
-    const uint32_t prev = atomicCAS(w, cur, nv);
-    if (prev == cur) return (cur >> sh) & 0xFFFFu;
-    cur = prev;
-  }
-}
-
 __device__ __forceinline__ uint32_t get16(uint32_t packed, int half) { return (packed >> (16 * half)) & 0xFFFFu; }
 
 // Fisher-Yates of every leaf of the super-block at once (Algorithm 1 per leaf).
@@ -79,7 +65,7 @@ __device__ __forceinline__ uint32_t get16(uint32_t packed, int half) { return (p
 // each of its slots.
 template <int BPT, int NT>
 __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uint32_t b, uint32_t u, uint32_t lt,
-                                                uint32_t tpl, uint32_t cnt, Key key, uint32_t* bits, uint32_t* status,
+                                                uint32_t tpl, Key key, uint32_t* bits, uint32_t* status,
                                                 uint32_t (&F)[BPT][2]) {
   constexpr uint32_t NONE = 0xFFFFu;
   uint16_t* const half = head;  // the lists' words, as 16-bit halves
@@ -471,7 +457,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
     const uint32_t line = (uint32_t)tid * per_line;
     if (line < cnt) touch = *reinterpret_cast<const uint32_t*>(in + base + line);
   }
-  leaf_fy_sources<BPT, NT>(head, lb, b, (uint32_t)u, lt, tpl, cnt, key, &bits, a.status, F);
+  leaf_fy_sources<BPT, NT>(head, lb, b, (uint32_t)u, lt, tpl, key, &bits, a.status, F);
   asm volatile("" ::"v"(touch));
   (void)nleaf;
 
@@ -875,7 +861,9 @@ static void launch_leaf_t(const LeafArgs& a, uint64_t grid, hipStream_t st) {
 
 // Super-block size: 64 KiB of elements with 512 threads (two workgroups per
 // CU, the default: measured faster), or 128 KiB with 1024 threads (one per
-// CU, MS_LEAF_BIG=1).  A tuning knob only: the permutation does not depend on it.
+// CU, MS_LEAF_BIG=1).  A tuning knob only: the permutation does not depend on
+// it.  16-byte leaves of cutoff + 1 = 4097 records do not fit the default
+// 4096-record super-block: the planner takes the 128 KiB one for them.
 static bool leaf_small() {
   static bool v = [] {
     const char* e = getenv("MS_LEAF_BIG");
@@ -884,17 +872,19 @@ static bool leaf_small() {
   return v;
 }
 
-int leaf_capacity(uint32_t eb) {
-  const int big = eb == 4 ? 32768 : eb == 8 ? 16384 : 8192;
-  return leaf_small() ? big / 2 : big;
+// Elements per super-block: the default size, or the 128 KiB one (`big`).
+int leaf_capacity(uint32_t eb, bool big) {
+  const int cap = eb == 4 ? 32768 : eb == 8 ? 16384 : 8192;
+  return big ? cap : cap / 2;
 }
+bool leaf_big_default() { return !leaf_small(); }
 int leaf_max_block() { return 4097; }
 int leaf_max_levels() { return 6; }
 
 void launch_leaf_multi(const LeafArgs* jobs, const uint32_t* wpre, uint32_t njobs, uint32_t nwg, uint32_t eb,
-                       hipStream_t st) {
+                       bool big, hipStream_t st) {
   if (!nwg) return;
-  const bool sm = leaf_small();
+  const bool sm = !big;
   const dim3 g(nwg);
   if (eb == 4) {
     if (sm) hipLaunchKernelGGL((leaf_multi_kernel<uint32_t, 16384, 512>), g, dim3(512), 0, st, jobs, wpre, njobs);
@@ -908,8 +898,8 @@ void launch_leaf_multi(const LeafArgs* jobs, const uint32_t* wpre, uint32_t njob
   }
 }
 
-void launch_leaf(const LeafArgs& a, uint32_t eb, bool ident, uint64_t grid, hipStream_t st) {
-  const bool sm = leaf_small();
+void launch_leaf(const LeafArgs& a, uint32_t eb, bool ident, bool big, uint64_t grid, hipStream_t st) {
+  const bool sm = !big;
   if (eb == 4) {
     if (ident) {
       if (sm) launch_leaf_t<uint32_t, 16384, 512, true>(a, grid, st);

@@ -23,6 +23,8 @@ CONFIGS = [
     ("perm_n2^20_seed1", 1 << 20, 1),
     ("perm_n2^27_seed11", 1 << 27, 11),
     ("perm_n2^30_seed7", 1 << 30, 7),
+    # the largest size the library accepts, 2^32 - 2^16 (about 33 GiB of host memory, several minutes)
+    ("perm_n2^32-2^16_seed5", (1 << 32) - (1 << 16), 5),
 ]
 
 

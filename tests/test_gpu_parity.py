@@ -107,8 +107,10 @@ def test_shuffle_u32_equals_permutation_of_identity(M, n):
 
 
 @pytest.mark.parametrize("eb", [8, 16])
-@pytest.mark.parametrize("n", [3, 4097, 20000, 123457])
+@pytest.mark.parametrize("n", [3, 4097, 8193, 20000, 123457, (1 << 20) + 7, 4096 * 2**9 + 300])
 def test_records_follow_the_index_permutation(M, eb, n):
+    # 8193, 2^20 + 7 and 4096 * 2^9 + 300 have leaves of cutoff + 1 = 4097
+    # elements (16-byte leaves of that size take the 128 KiB super-block)
     import torch
 
     _say(f"[gpu] records eb={eb} n={n}")

@@ -47,6 +47,17 @@ def test_plan_matches_the_driver_partition():
     assert p["lds_levels"] == 0 and p["levels"] == p["hbm_levels"]
 
 
+def test_leaves_of_cutoff_plus_one_plan_for_every_element_size():
+    # the partition [n*i/q, n*(i+1)/q) makes leaves of cutoff + 1 elements for
+    # most n that are not powers of two (Appendix A.2); every element size
+    # must accept them
+    M, _ = _lib()
+    for n in (8193, (1 << 20) + 7, (1 << 27) + 5, 4096 * 2**9 + 300, (1 << 32) - (1 << 16)):
+        for eb in (4, 8, 16):
+            p = M.plan(n, eb)
+            assert -(-n // p["leaves"]) <= 4097
+
+
 def test_levels_per_pass_default_and_knob():
     # default: 3 levels per pass, 4 from 13 HBM levels on (for 4-byte
     # elements only when 3 does not divide them); the passes split the
