@@ -135,6 +135,24 @@ int ms_permutation_ex(uint32_t* out, uint64_t n, uint64_t seed, void* stream, co
 int ms_shuffle_batched_ex(void* const* ptrs, const uint64_t* sizes, const uint32_t* elem_bytes, uint32_t count,
                           uint64_t seed, void* stream, const ms_config* cfg, unsigned long long* d_bits_per_array);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): the same
+ * result as ms_shuffle_ex with the same arguments, but the library allocates
+ * nothing.  Its scratch -- a status word, the array copy and the merge plan --
+ * lives in one fixed device array of 64 MiB (MS_NOALLOC_SCRATCH_BYTES) per
+ * device, which each device holds until the process ends; a call whose
+ * scratch (256 + ms_scratch_bytes, rounded up) exceeds it returns
+ * MS_ERR_UNSUPPORTED before launching anything (4-byte arrays up to about
+ * 2^23 elements fit).  Every kernel runs on `stream` in order (no side stream,
+ * no events).  All calls on one device share the array, which keeps the last
+ * call's contents: calls that overlap in time on one device (on different
+ * streams or from different host threads) race and give wrong results; calls
+ * on one stream are ordered and safe.  Status flags as for ms_shuffle, read by
+ * ms_device_status. */
+#define MS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int ms_shuffle_noalloc(void* dev_ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed, void* stream,
+                       const ms_config* cfg, unsigned long long* d_bits);
+
 /* Plan of one call, computed on the host (no GPU needed). */
 typedef struct ms_plan_info {
   uint32_t levels;        /* c */

@@ -6,7 +6,7 @@ See include/mergeshuffle.h for the C entry points; this package holds the
 kernels (csrc/), their build (build.py) and a thin ctypes binding (_lib.py).
 """
 from ._lib import (MSError, device_status, lib, permutation, plan, profile_enable, profile_read, release,
-                   shuffle_, shuffle_batched_)
+                   shuffle_, shuffle_batched_, shuffle_noalloc_)
 
 __all__ = ["MSError", "device_status", "lib", "permutation", "plan", "profile_enable", "profile_read",
-           "release", "shuffle_", "shuffle_batched_"]
+           "release", "shuffle_", "shuffle_batched_", "shuffle_noalloc_"]

@@ -25,8 +25,9 @@ MS_CFG_PLACEMENT_R1 = 4
 SYMBOLS = [
     "ms_shuffle", "ms_permutation", "ms_shuffle_batched", "ms_shuffle_ex", "ms_permutation_ex",
     "ms_shuffle_batched_ex", "ms_plan", "ms_scratch_bytes", "ms_leaf_B_for", "ms_device_status",
-    "ms_release", "ms_last_error", "ms_profile_enable", "ms_profile_read",
+    "ms_release", "ms_last_error", "ms_profile_enable", "ms_profile_read", "ms_shuffle_noalloc",
 ]
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class MSConfig(ctypes.Structure):
@@ -66,6 +67,7 @@ def lib():
         L.ms_permutation_ex.argtypes = [vp, u64, u64, vp, cfgp, vp]
         L.ms_shuffle_batched_ex.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(u64), ctypes.POINTER(u32), u32,
                                             u64, vp, cfgp, vp]
+        L.ms_shuffle_noalloc.argtypes = [vp, u64, u32, u64, vp, cfgp, vp]
         L.ms_plan.argtypes = [u64, u32, cfgp, ctypes.POINTER(MSPlanInfo)]
         L.ms_scratch_bytes.argtypes = [u64, u32]
         L.ms_scratch_bytes.restype = u64
@@ -78,6 +80,7 @@ def lib():
         L.ms_profile_enable.argtypes = [i32]
         L.ms_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64)]
         for name in ("ms_shuffle", "ms_permutation", "ms_shuffle_batched", "ms_shuffle_ex", "ms_permutation_ex",
+                     "ms_shuffle_noalloc",
                      "ms_shuffle_batched_ex", "ms_plan", "ms_device_status", "ms_release", "ms_profile_enable",
                      "ms_profile_read"):
             getattr(L, name).restype = i32
@@ -126,6 +129,20 @@ def shuffle_(t, seed: int, *, stream=None, bits=None, leaf_B=0, lds_levels_max=0
     rc = lib().ms_shuffle_ex(_ptr(t), n, eb, seed & (2**64 - 1), _stream(stream),
                              _cfg(leaf_B, lds_levels_max, hbm_only, levels_per_pass, one_level_passes, placement),
                              ctypes.c_void_p(bits.data_ptr()) if bits is not None else None)
+    _check(rc)
+    return t
+
+
+def shuffle_noalloc_(t, seed: int, *, stream=None, bits=None, leaf_B=0, lds_levels_max=0, hbm_only=False,
+                     levels_per_pass=0, one_level_passes=False, placement="R2"):
+    """As shuffle_, through the entry point that allocates nothing (scratch in a
+    fixed 64 MiB device array shared by every such call on the device)."""
+    assert t.is_cuda and t.is_contiguous()
+    eb = t.element_size() * (t[0].numel() if t.dim() > 1 else 1)
+    rc = lib().ms_shuffle_noalloc(_ptr(t), t.shape[0], eb, seed & (2**64 - 1), _stream(stream),
+                                  _cfg(leaf_B, lds_levels_max, hbm_only, levels_per_pass, one_level_passes,
+                                       placement),
+                                  ctypes.c_void_p(bits.data_ptr()) if bits is not None else None)
     _check(rc)
     return t
 

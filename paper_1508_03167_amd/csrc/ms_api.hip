@@ -542,6 +542,55 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
                       d_bits ? d_bits : dc->dummy_bits, dc->status, ident, true);
 }
 
+// ---------------------------------------------------------------------------
+// calls that allocate nothing: scratch in a fixed device array
+// ---------------------------------------------------------------------------
+// Layout: the status word (byte 0) and a bit counter for calls without one
+// (byte 64) in the first 256 bytes, then the array copy, then the plan.
+constexpr size_t kNoAllocBytes = 64ull << 20;
+constexpr size_t kNoAllocHead = 256;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Device address of `scratch` on each device (its host-side name is not a
+// device address), resolved once per device with that device current.
+void* g_noalloc_ptr[64] = {};
+
+int noalloc_area(char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(MS_ERR_HIP, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(MS_ERR_HIP, "hipGetSymbolAddress(scratch) gave a null address");
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = reinterpret_cast<char*>(g_noalloc_ptr[dev]);
+  return MS_OK;
+}
+
+int run_noalloc(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, const ms_config* cfg,
+                unsigned long long* d_bits) {
+  HostPlan hp;
+  int rc = make_plan(n, eb, cfg, hp);
+  if (rc) return rc;
+  if ((rc = check_args(hp, ptr))) return rc;
+  const size_t data = hp.nlev ? align256(n * eb) : 0;
+  const size_t need = kNoAllocHead + data + hp.lay.bytes;
+  if (need > kNoAllocBytes)
+    return fail(MS_ERR_UNSUPPORTED, "n = %llu needs %zu bytes of scratch, above the %zu of the allocation-free entry point",
+                (unsigned long long)n, need, kNoAllocBytes);
+  if (n <= 1) return MS_OK;
+  char* area;
+  if ((rc = noalloc_area(&area))) return rc;
+  unsigned long long* bits = d_bits ? d_bits : reinterpret_cast<unsigned long long*>(area + 64);
+  uint32_t* status = reinterpret_cast<uint32_t*>(area);
+  // every kernel on the caller's stream, in order; no events, no profiling
+  return enqueue_call(hp, ptr, area + kNoAllocHead, area + kNoAllocHead + data, seed, st, nullptr, nullptr,
+                      nullptr, bits, status, false, false);
+}
+
 // The arrays of a batched call with at most kWaveMaxN elements run in
 // waves: per wave, one launch per plan stage for all of its arrays that need
 // HBM passes, one leaf launch per element size and one launch per (fused
@@ -776,6 +825,12 @@ int ms_shuffle_ex(void* dev_ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed,
   return run_one(dev_ptr, n, elem_bytes, seed, reinterpret_cast<hipStream_t>(stream), cfg, d_bits, false);
 }
 
+int ms_shuffle_noalloc(void* dev_ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed, void* stream,
+                       const ms_config* cfg, unsigned long long* d_bits) {
+  g_err.clear();
+  return run_noalloc(dev_ptr, n, elem_bytes, seed, reinterpret_cast<hipStream_t>(stream), cfg, d_bits);
+}
+
 int ms_shuffle(void* dev_ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed, void* stream) {
   return ms_shuffle_ex(dev_ptr, n, elem_bytes, seed, stream, nullptr, nullptr);
 }
@@ -908,9 +963,22 @@ int ms_device_status(void* stream, uint32_t* flags) {
     if ((rc = device_ctx(&dc))) return rc;
   }
   HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
-  uint32_t v = 0;
+  uint32_t v = 0, w = 0;
   HIP_TRY(hipMemcpy(&v, dc->status, 4, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemset(dc->status, 0, 4));
+  // the allocation-free calls' flags, if that entry point has run on this device
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  void* na = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    na = g_noalloc_ptr[dev];
+  }
+  if (na) {
+    HIP_TRY(hipMemcpy(&w, na, 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(na, 0, 4));
+  }
+  v |= w;
   if (flags) *flags = v;
   return v ? MS_ERR_CAPACITY : MS_OK;
 }
