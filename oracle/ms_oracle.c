@@ -52,6 +52,7 @@
 
 #define ORACLE_R2 0
 #define ORACLE_R1 1
+#define ORACLE_BALANCED 2
 
 /* ------------------------------------------------------------------ */
 /* Philox-4x32-10, Salmon, Moraes, Dror, Shaw (SC'11), Section 4.     */
@@ -268,6 +269,60 @@ static uint64_t merge_r1(osrc *s, uint32_t *t, uint64_t n1, uint64_t n2,
 }
 
 /* ------------------------------------------------------------------ */
+/* BalancedShuffle's merge (Section 2): the two shuffled halves are    */
+/* interleaved by a word drawn uniformly from C(n1+n2, n1) -- n1 0's   */
+/* (take from A) and n2 1's (take from B) -- each half keeping its     */
+/* order; Section 2.2 shows this map from S_n1 x S_n2 x C(n1+n2, n1)   */
+/* to S_(n1+n2) is a bijection, so the result is uniform.              */
+/*                                                                    */
+/* The paper takes the word from the generator of [BaBoJa14], which it */
+/* does not describe.  Reading used here: the word is the sequence of  */
+/* side labels (0 = A, 1 = B) that Algorithm 2 produces when it merges */
+/* the labels 0^n1 and 1^n2 -- coin flips until a flip falls on an    */
+/* exhausted side, the rest of the other side, then the Fisher-Yates   */
+/* insertion of slots P..N-1 with partners drawn in [0, i].  Lemma 1   */
+/* makes Algorithm 2's output a uniform arrangement of any two         */
+/* uniformly shuffled halves, so the labels it leaves are a uniform    */
+/* element of C(n1+n2, n1).  It uses the same bits as Algorithm 2.     */
+/* ------------------------------------------------------------------ */
+static uint64_t merge_balanced(osrc *s, uint32_t *t, uint64_t n1, uint64_t n2,
+                               uint32_t L, uint32_t m, uint32_t *tmp, uint8_t *word)
+{
+    const uint32_t *A = t, *B = t + n1;
+    uint64_t n = n1 + n2, a = 0, b = 0, step = 0, P, i, k;
+    /* the balanced word */
+    for (;;) {
+        int w = random_bit(s, L, m, step);
+        step += 1;
+        if (w == 0) {
+            if (a == n1) break;
+            word[a + b] = 0;
+            a += 1;
+        } else {
+            if (b == n2) break;
+            word[a + b] = 1;
+            b += 1;
+        }
+    }
+    P = a + b;
+    while (a < n1) { word[a + b] = 0; a += 1; }
+    while (b < n2) { word[a + b] = 1; b += 1; }
+    for (i = P; i < n; i++) {
+        uint64_t j = random_int(s, L, m, i, i + 1);
+        uint8_t x = word[i]; word[i] = word[j]; word[j] = x;
+    }
+    /* the interleave it defines: slot k takes the next element of the
+     * side its letter names */
+    a = b = 0;
+    for (k = 0; k < n; k++) {
+        if (word[k] == 0) tmp[k] = A[a++];
+        else tmp[k] = B[b++];
+    }
+    memcpy(t, tmp, n * sizeof(uint32_t));
+    return P;
+}
+
+/* ------------------------------------------------------------------ */
 /* Algorithm MergeShuffle / Appendix A.2 shuffle().                    */
 /* ------------------------------------------------------------------ */
 static uint32_t levels_for(uint64_t n, uint64_t cutoff)
@@ -288,13 +343,18 @@ static uint64_t run_shuffle(osrc *proto, uint32_t *t, uint64_t n, uint64_t cutof
     uint32_t c, L;
     uint64_t q, i, bits = 0;
     uint32_t *tmp = NULL;
+    uint8_t *word = NULL;
     (void)threads;
     if (n <= 1 || cutoff < 1) return 0;
     c = levels_for(n, cutoff);
     q = (uint64_t)1 << c;
-    if (placement == ORACLE_R2) {
+    if (placement == ORACLE_R2 || placement == ORACLE_BALANCED) {
         tmp = (uint32_t *)malloc(n * sizeof(uint32_t));
         if (!tmp) return ~(uint64_t)0;
+    }
+    if (placement == ORACLE_BALANCED) {
+        word = (uint8_t *)malloc(n);
+        if (!word) { free(tmp); return ~(uint64_t)0; }
     }
 
     /* leaves: one Fisher-Yates per block (parallel over blocks, as the
@@ -326,6 +386,8 @@ static uint64_t run_shuffle(osrc *proto, uint32_t *t, uint64_t n, uint64_t cutof
             s.bits = 0; s.memo_ok = 0;
             if (placement == ORACLE_R2)
                 P = merge_r2(sp, t + j, k - j, l - k, L, (uint32_t)m, tmp + j);
+            else if (placement == ORACLE_BALANCED)
+                P = merge_balanced(sp, t + j, k - j, l - k, L, (uint32_t)m, tmp + j, word + j);
             else
                 P = merge_r1(sp, t + j, k - j, l - k, L, (uint32_t)m);
             /* merges of level L are stored after those of levels 1..L-1 */
@@ -334,6 +396,7 @@ static uint64_t run_shuffle(osrc *proto, uint32_t *t, uint64_t n, uint64_t cutof
         }
     }
     free(tmp);
+    free(word);
     return bits;
 }
 
@@ -394,13 +457,17 @@ uint64_t oracle_merge_scripted(uint32_t *t, uint64_t n1, uint64_t n2, int placem
     osrc s;
     uint64_t P;
     uint32_t *tmp;
+    uint8_t *word;
     memset(&s, 0, sizeof s);
     s.script = script;
     s.script_len = script_len;
     tmp = (uint32_t *)malloc((n1 + n2 + 1) * sizeof(uint32_t));
+    word = (uint8_t *)malloc(n1 + n2 + 1);
     if (placement == ORACLE_R2) P = merge_r2(&s, t, n1, n2, 1, 0, tmp);
+    else if (placement == ORACLE_BALANCED) P = merge_balanced(&s, t, n1, n2, 1, 0, tmp, word);
     else P = merge_r1(&s, t, n1, n2, 1, 0);
     free(tmp);
+    free(word);
     if (need) *need = s.starved ? s.need : 0;
     return s.starved ? ~(uint64_t)0 : P;
 }
@@ -412,12 +479,16 @@ uint64_t oracle_merge_seeded(uint32_t *t, uint64_t n1, uint64_t n2, int placemen
     osrc s;
     uint64_t P;
     uint32_t *tmp;
+    uint8_t *word;
     memset(&s, 0, sizeof s);
     s.seed = seed;
     tmp = (uint32_t *)malloc((n1 + n2 + 1) * sizeof(uint32_t));
+    word = (uint8_t *)malloc(n1 + n2 + 1);
     if (placement == ORACLE_R2) P = merge_r2(&s, t, n1, n2, L, m, tmp);
+    else if (placement == ORACLE_BALANCED) P = merge_balanced(&s, t, n1, n2, L, m, tmp, word);
     else P = merge_r1(&s, t, n1, n2, L, m);
     free(tmp);
+    free(word);
     if (bits) *bits += s.bits;
     return P;
 }

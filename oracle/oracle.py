@@ -20,6 +20,7 @@ _LIB = os.path.join(_HERE, "libms_oracle.so")
 
 R2 = 0  # stable interleave placement (the contract)
 R1 = 1  # in-place swap placement of the printed listing
+BALANCED = 2  # BalancedShuffle (Section 2): interleave by a uniform word of C(n1+n2, n1)
 
 _lib = None
 
