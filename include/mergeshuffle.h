@@ -153,6 +153,14 @@ int ms_shuffle_batched_ex(void* const* ptrs, const uint64_t* sizes, const uint32
 int ms_shuffle_noalloc(void* dev_ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed, void* stream,
                        const ms_config* cfg, unsigned long long* d_bits);
 
+/* As ms_shuffle_batched_ex, with an explicit seed per array: array a ends
+ * exactly as ms_shuffle_ex(ptrs[a], sizes[a], elem_bytes[a], seeds[a], ...)
+ * leaves it (seeds: host array of count seeds).  For callers that batch
+ * unrelated requests, such as a serving loop. */
+int ms_shuffle_batched_seeds(void* const* ptrs, const uint64_t* sizes, const uint32_t* elem_bytes,
+                             const uint64_t* seeds, uint32_t count, void* stream, const ms_config* cfg,
+                             unsigned long long* d_bits_per_array);
+
 /* Plan of one call, computed on the host (no GPU needed). */
 typedef struct ms_plan_info {
   uint32_t levels;        /* c */

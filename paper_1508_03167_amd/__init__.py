@@ -6,7 +6,9 @@ See include/mergeshuffle.h for the C entry points; this package holds the
 kernels (csrc/), their build (build.py) and a thin ctypes binding (_lib.py).
 """
 from ._lib import (MSError, device_status, lib, permutation, plan, profile_enable, profile_read, release,
-                   shuffle_, shuffle_batched_, shuffle_noalloc_)
+                   scratch_bytes, shuffle_, shuffle_batched_, shuffle_batched_seeds_,
+                   shuffle_noalloc_)
 
 __all__ = ["MSError", "device_status", "lib", "permutation", "plan", "profile_enable", "profile_read",
-           "release", "shuffle_", "shuffle_batched_", "shuffle_noalloc_"]
+           "release", "scratch_bytes", "shuffle_", "shuffle_batched_",
+           "shuffle_batched_seeds_", "shuffle_noalloc_"]

@@ -26,6 +26,7 @@ SYMBOLS = [
     "ms_shuffle", "ms_permutation", "ms_shuffle_batched", "ms_shuffle_ex", "ms_permutation_ex",
     "ms_shuffle_batched_ex", "ms_plan", "ms_scratch_bytes", "ms_leaf_B_for", "ms_device_status",
     "ms_release", "ms_last_error", "ms_profile_enable", "ms_profile_read", "ms_shuffle_noalloc",
+    "ms_shuffle_batched_seeds",
 ]
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -68,6 +69,8 @@ def lib():
         L.ms_shuffle_batched_ex.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(u64), ctypes.POINTER(u32), u32,
                                             u64, vp, cfgp, vp]
         L.ms_shuffle_noalloc.argtypes = [vp, u64, u32, u64, vp, cfgp, vp]
+        L.ms_shuffle_batched_seeds.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(u64), ctypes.POINTER(u32),
+                                               ctypes.POINTER(u64), u32, vp, cfgp, vp]
         L.ms_plan.argtypes = [u64, u32, cfgp, ctypes.POINTER(MSPlanInfo)]
         L.ms_scratch_bytes.argtypes = [u64, u32]
         L.ms_scratch_bytes.restype = u64
@@ -80,7 +83,7 @@ def lib():
         L.ms_profile_enable.argtypes = [i32]
         L.ms_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64)]
         for name in ("ms_shuffle", "ms_permutation", "ms_shuffle_batched", "ms_shuffle_ex", "ms_permutation_ex",
-                     "ms_shuffle_noalloc",
+                     "ms_shuffle_noalloc", "ms_shuffle_batched_seeds",
                      "ms_shuffle_batched_ex", "ms_plan", "ms_device_status", "ms_release", "ms_profile_enable",
                      "ms_profile_read"):
             getattr(L, name).restype = i32
@@ -170,6 +173,27 @@ def shuffle_batched_(tensors, seed: int, *, stream=None, bits=None, leaf_B=0, pl
                                      ctypes.c_void_p(bits.data_ptr()) if bits is not None else None)
     _check(rc)
     return tensors
+
+
+def shuffle_batched_seeds_(tensors, seeds, *, stream=None, bits=None, leaf_B=0):
+    """Shuffle each device tensor of the list in place; tensor a uses seeds[a]."""
+    cnt = len(tensors)
+    if len(seeds) != cnt:
+        raise ValueError("one seed per tensor")
+    ptrs = (ctypes.c_void_p * max(cnt, 1))(*[t.data_ptr() for t in tensors])
+    sizes = (ctypes.c_uint64 * max(cnt, 1))(*[t.shape[0] for t in tensors])
+    ebs = (ctypes.c_uint32 * max(cnt, 1))(
+        *[t.element_size() * (t[0].numel() if t.dim() > 1 else 1) for t in tensors])
+    sds = (ctypes.c_uint64 * max(cnt, 1))(*[int(s) & (2**64 - 1) for s in seeds])
+    rc = lib().ms_shuffle_batched_seeds(ptrs, sizes, ebs, sds, cnt, _stream(stream), _cfg(leaf_B),
+                                        ctypes.c_void_p(bits.data_ptr()) if bits is not None else None)
+    _check(rc)
+    return tensors
+
+
+def scratch_bytes(n: int, elem_bytes: int = 4) -> int:
+    """Library scratch a call of this size needs (0 if unsupported)."""
+    return int(lib().ms_scratch_bytes(n, elem_bytes))
 
 
 def plan(n: int, elem_bytes: int = 4, leaf_B=0, lds_levels_max=0, hbm_only=False, levels_per_pass=0,

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmergeshuffle.so")
-SOURCES = ["ms_api.hip", "ms_kernels_plan.hip", "ms_kernels_data.hip", "ms_kernels_group.hip"]
+SOURCES = ["ms_api.hip", "ms_kernels_plan.hip", "ms_kernels_data.hip", "ms_kernels_group.hip", "ms_kernels_pass.hip"]
 ARCH = os.environ.get("MS_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -25,6 +25,14 @@
 namespace ms {
 void launch_group(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st);
 int group_tile(uint32_t eb);
+void launch_pass_group(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st);
+int pass_group_tile(uint32_t eb);
+void launch_pass_group_multi(const GroupArgs* jobs, const uint32_t* tpre, uint32_t njobs, uint32_t ntiles, int lam,
+                             uint32_t eb, hipStream_t st);
+uint32_t pass_desc_words(uint32_t eb, int lam);
+void launch_pass_desc(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st);
+void launch_pass_desc_multi(const GroupArgs* jobs, const uint32_t* tpre, uint32_t njobs, uint32_t ntiles, int lam,
+                            uint32_t eb, hipStream_t st);
 void launch_plan(const PlanArgs& pa, hipStream_t st);
 void launch_plan_multi(const PlanArgs* pas, uint32_t njobs, const uint32_t* const* pre, const uint32_t* units,
                        hipStream_t st);
@@ -66,6 +74,27 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr uint64_t kMaxN = (1ull << 32) - (1ull << 16);
+
+// Fused-pass kernel: the word-aligned table pass (default) or the earlier
+// window-tree pass (MS_PASS_IMPL=tree), kept for comparison.  The
+// permutation does not depend on the choice.
+bool pass_tree() {
+  static const bool v = [] {
+    const char* e = getenv("MS_PASS_IMPL");
+    return e && strcmp(e, "tree") == 0;
+  }();
+  return v;
+}
+int fused_tile(uint32_t eb) { return pass_tree() ? group_tile(eb) : pass_group_tile(eb); }
+void launch_fused(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st) {
+  if (pass_tree()) launch_group(a, lam, eb, grid, st);
+  else launch_pass_group(a, lam, eb, grid, st);
+}
+void launch_fused_multi(const GroupArgs* jobs, const uint32_t* tpre, uint32_t njobs, uint32_t ntiles, int lam,
+                        uint32_t eb, hipStream_t st) {
+  if (pass_tree()) launch_group_multi(jobs, tpre, njobs, ntiles, lam, eb, st);
+  else launch_pass_group_multi(jobs, tpre, njobs, ntiles, lam, eb, st);
+}
 constexpr uint32_t kDefaultB = 4096;
 
 // ---------------------------------------------------------------------------
@@ -73,7 +102,7 @@ constexpr uint32_t kDefaultB = 4096;
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t zloc, ctot, zc, zg, P, side, kcnt, toff, tail_src, bcnt, bfill, boff, part, pool_x, pool_step, pool_src,
-      tail_xsrc, pool_xsrc, bnd, bits_part;
+      tail_xsrc, pool_xsrc, bnd, desc, bits_part;
   size_t bytes;
 };
 
@@ -87,6 +116,8 @@ struct HostPlan {
   uint32_t ngroup = 0;
   uint32_t gfirst[kMaxLevels];    // first HBM level index of each group
   uint32_t glam[kMaxLevels];      // levels in each group
+  uint64_t gdesc_first[kMaxLevels];  // first word of each group's tile descriptors (table pass)
+  uint32_t gdesc_words[kMaxLevels];  // words per tile descriptor
   PlanArgs pa;
   Layout lay;
 };
@@ -189,9 +220,9 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
       l += sz;
     }
   }
-  uint64_t all_bnd = 0;
+  uint64_t all_bnd = 0, all_desc = 0;
   if (hp.fused) {
-    const uint32_t Tg = (uint32_t)group_tile(eb);
+    const uint32_t Tg = (uint32_t)fused_tile(eb);
     tiles = 0;
     for (uint32_t g = 0; g < hp.ngroup; ++g) {
       const HbmLevel& top = pa.lev[hp.gfirst[g] + hp.glam[g] - 1];
@@ -201,6 +232,10 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
       gi.T = Tg;
       gi.tpm = (top.nmax + Tg - 1) / Tg;
       gi.bnd_first = all_bnd;
+      // the table pass reads one descriptor per tile, built by the plan
+      hp.gdesc_words[g] = pass_tree() ? 0u : pass_desc_words(eb, (int)gi.lam);
+      hp.gdesc_first[g] = all_desc;
+      all_desc += (uint64_t)top.nmerge * gi.tpm * hp.gdesc_words[g];
       for (uint32_t k = 0; k < gi.lam; ++k) {
         pa.lev[gi.lf + k].grp = g;
         pa.lev[gi.lf + k].gli = k;
@@ -212,6 +247,7 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
     pa.ngroup = hp.ngroup;
   }
   pa.total_bnd = all_bnd;
+  pa.total_desc = all_desc;
   pa.total_chunks = chunks;
   pa.total_merges = merges;
   pa.total_buckets = buckets;
@@ -241,6 +277,7 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
   y.tail_xsrc = hp.fused ? take(cap * 4) : 0;
   y.pool_xsrc = hp.fused ? take(cap * 4) : 0;
   y.bnd = hp.fused ? take(all_bnd * kBndStride * 4) : 0;
+  y.desc = hp.fused ? take(all_desc * 4) : 0;
   y.bits_part = take(kBitsParts * 8);
   y.bytes = hp.nlev ? o : 0;
   return MS_OK;
@@ -373,6 +410,7 @@ void bind_plan(HostPlan& hp, void* area) {
   pa.tail_xsrc = hp.fused ? reinterpret_cast<uint32_t*>(b + y.tail_xsrc) : nullptr;
   pa.pool_xsrc = hp.fused ? reinterpret_cast<uint32_t*>(b + y.pool_xsrc) : nullptr;
   pa.bnd = hp.fused ? reinterpret_cast<uint32_t*>(b + y.bnd) : nullptr;
+  pa.desc = hp.fused ? reinterpret_cast<uint32_t*>(b + y.desc) : nullptr;
   pa.bits_part = reinterpret_cast<unsigned long long*>(b + y.bits_part);
 }
 
@@ -401,6 +439,8 @@ GroupArgs group_args(const HostPlan& hp, uint32_t g, const void* cur, void* othe
   ga.pool_xsrc = pa.pool_xsrc;
   ga.tail_cap = pa.tail_cap;
   ga.pool_cap = pa.pool_cap;
+  ga.desc = pa.desc ? pa.desc + hp.gdesc_first[g] : nullptr;
+  ga.desc_words = hp.gdesc_words[g];
   for (uint32_t k = 0; k < gi.lam; ++k) {
     const HbmLevel& lv = pa.lev[gi.lf + k];
     ga.L[k] = lv.L;
@@ -441,6 +481,19 @@ int enqueue_call(HostPlan& hp, void* X, void* Y, void* plan_area, uint64_t seed,
     {
       ProfScope ps(prof ? 0 : -1, fork ? plan_st : st);
       launch_plan(pa, fork ? plan_st : st);
+      // the tile descriptors of every fused pass (each pass reads the
+      // buffer the previous one wrote: the same alternation as below)
+      if (hp.fused && !pass_tree()) {
+        void* c = (hp.ngroup % 2 == 0) ? X : Y;
+        for (uint32_t g = 0; g < hp.ngroup; ++g) {
+          void* o = c == X ? Y : X;
+          const GroupInfo& gi = pa.grp[g];
+          const GroupArgs ga = group_args(hp, g, c, o);
+          launch_pass_desc(ga, (int)gi.lam, eb, (uint64_t)pa.lev[gi.lf + gi.lam - 1].nmerge * gi.tpm,
+                           fork ? plan_st : st);
+          c = o;
+        }
+      }
     }
     if (fork) HIP_TRY(hipEventRecord(plan_join, plan_st));
   }
@@ -468,7 +521,7 @@ int enqueue_call(HostPlan& hp, void* X, void* Y, void* plan_area, uint64_t seed,
     const HbmLevel& top = pa.lev[gi.lf + gi.lam - 1];
     {
       ProfScope ps(prof ? 2 : -1, st);
-      launch_group(ga, (int)gi.lam, eb, (uint64_t)top.nmerge * gi.tpm, st);
+      launch_fused(ga, (int)gi.lam, eb, (uint64_t)top.nmerge * gi.tpm, st);
     }
     cur = other;
   }
@@ -635,7 +688,9 @@ int stage_buffer(Arena& ar, size_t bytes, void** out, int* which) {
   return MS_OK;
 }
 
+// seeds: per-array seeds, or null for seed + array index.
 int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<uint32_t>& idx, uint64_t seed,
+              const uint64_t* seeds,
               hipStream_t st, unsigned long long* d_bits, DeviceCtx* dc) {
   Arena* arp;
   {
@@ -729,7 +784,7 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
     for (uint32_t j = 0; j < nw; ++j) {
       HostPlan& hp = hps[i0 + j];
       const uint32_t a = idx[i0 + j];
-      const uint64_t sa = seed + a;
+      const uint64_t sa = seeds ? seeds[a] : seed + a;
       unsigned long long* bits = d_bits ? d_bits + a : dc->dummy_bits;
       void* X = ptrs[a];
       void* Y = hp.nlev ? d + data_off[j] : X;
@@ -792,6 +847,15 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
       for (int k = 0; k < kUnits; ++k) pre[k] = reinterpret_cast<const uint32_t*>(d + pre_off[k]);
       ProfScope ps(0, st);
       launch_plan_multi(reinterpret_cast<const PlanArgs*>(d + pa_off), np, pre, units, st);
+      if (!pass_tree()) {
+        for (auto& kv : gsec) {
+          const uint32_t key = kv.first;
+          const uint32_t lam = key % 4 + 1, cls = (key / 4) % 3;
+          launch_pass_desc_multi(reinterpret_cast<const GroupArgs*>(d + kv.second.off),
+                                 reinterpret_cast<const uint32_t*>(d + kv.second.tpre_off), kv.second.n,
+                                 kv.second.tiles, (int)lam, cls == 0 ? 4u : cls == 1 ? 8u : 16u, st);
+        }
+      }
     }
     for (int c = 0; c < kLeafCls; ++c) {
       if (!nleaf[c]) continue;
@@ -804,7 +868,7 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
       const uint32_t key = kv.first;
       const uint32_t lam = key % 4 + 1, cls = (key / 4) % 3;
       ProfScope ps(2, st);
-      launch_group_multi(reinterpret_cast<const GroupArgs*>(d + kv.second.off),
+      launch_fused_multi(reinterpret_cast<const GroupArgs*>(d + kv.second.off),
                          reinterpret_cast<const uint32_t*>(d + kv.second.tpre_off), kv.second.n, kv.second.tiles,
                          (int)lam, cls == 0 ? 4u : cls == 1 ? 8u : 16u, st);
     }
@@ -845,9 +909,27 @@ int ms_permutation(uint32_t* out, uint64_t n, uint64_t seed) {
   return ms_permutation_ex(out, n, seed, nullptr, nullptr, nullptr);
 }
 
+static int run_batched(void* const* ptrs, const uint64_t* sizes, const uint32_t* elem_bytes, uint32_t count,
+                       uint64_t seed, const uint64_t* seeds, void* stream, const ms_config* cfg,
+                       unsigned long long* d_bits_per_array);
+
 int ms_shuffle_batched_ex(void* const* ptrs, const uint64_t* sizes, const uint32_t* elem_bytes, uint32_t count,
                           uint64_t seed, void* stream, const ms_config* cfg, unsigned long long* d_bits_per_array) {
   g_err.clear();
+  return run_batched(ptrs, sizes, elem_bytes, count, seed, nullptr, stream, cfg, d_bits_per_array);
+}
+
+int ms_shuffle_batched_seeds(void* const* ptrs, const uint64_t* sizes, const uint32_t* elem_bytes,
+                             const uint64_t* seeds, uint32_t count, void* stream, const ms_config* cfg,
+                             unsigned long long* d_bits_per_array) {
+  g_err.clear();
+  if (count && !seeds) return fail(MS_ERR_INVALID, "null seed array");
+  return run_batched(ptrs, sizes, elem_bytes, count, 0, seeds, stream, cfg, d_bits_per_array);
+}
+
+static int run_batched(void* const* ptrs, const uint64_t* sizes, const uint32_t* elem_bytes, uint32_t count,
+                       uint64_t seed, const uint64_t* seeds, void* stream, const ms_config* cfg,
+                       unsigned long long* d_bits_per_array) {
   if (count == 0) return MS_OK;
   if (!ptrs || !sizes) return fail(MS_ERR_INVALID, "null pointer or size array");
   const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -901,10 +983,11 @@ int ms_shuffle_batched_ex(void* const* ptrs, const uint64_t* sizes, const uint32
     const uint32_t a = large[i];
     const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
     const hipStream_t s2 = side ? dc->side[i % kSideStreams] : st;
-    err = run_one(ptrs[a], sizes[a], eb, seed + a, s2, cfg, d_bits_per_array ? d_bits_per_array + a : nullptr, false);
+    err = run_one(ptrs[a], sizes[a], eb, seeds ? seeds[a] : seed + a, s2, cfg,
+                  d_bits_per_array ? d_bits_per_array + a : nullptr, false);
   }
   if (err == MS_OK && !wave_idx.empty())
-    err = run_waves(ptrs, wave_hp, wave_idx, seed, st, d_bits_per_array, dc);
+    err = run_waves(ptrs, wave_hp, wave_idx, seed, seeds, st, d_bits_per_array, dc);
   if (side) {
     // joined even after an error, so that the caller's stream still orders
     // after whatever was launched

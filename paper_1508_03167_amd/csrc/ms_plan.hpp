@@ -89,6 +89,8 @@ struct PlanArgs {
   uint32_t* pool_xsrc;    // as pool_src, traced down to the input of the fused pass
   uint32_t* bnd;          // boundary records of every fused pass
   uint64_t total_bnd;
+  uint32_t* desc;         // tile descriptors of every fused pass
+  uint64_t total_desc;    // their words
   unsigned long long* bits;
   unsigned long long* bits_part;  // kBitsParts partial sums of the insertion-loop draws' bits
   uint32_t* status;
@@ -98,6 +100,9 @@ struct PlanArgs {
   GroupInfo grp[kMaxLevels];
 };
 
+
+// Kernels take PlanArgs by value: it must fit the 4 KiB kernel-argument block.
+static_assert(sizeof(PlanArgs) <= 4096, "PlanArgs exceeds the kernel-argument limit");
 
 // Arguments of the data kernels (shared by the host runtime and the kernels).
 struct LeafArgs {
@@ -144,6 +149,9 @@ struct GroupArgs {
   const uint32_t* pool_x;     // target entry: slot
   const uint32_t* pool_xsrc;  // target entry: pass-input offset of the slot's final value, or ~0
   uint64_t tail_cap, pool_cap;
+  uint32_t* desc;             // tile descriptors of this pass (built by the plan, read by the pass)
+  uint32_t desc_words;        // 32-bit words per tile descriptor
+  uint32_t pad2;
   // per level of the pass, bottom first
   uint32_t L[kGroupMax];
   uint32_t blog[kGroupMax];
