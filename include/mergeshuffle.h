@@ -49,8 +49,10 @@
  * keeps the insertion-loop tables of every level in capacity-bounded pools
  * sized far above the expected need (the chance that a call exceeds them is
  * below 2^-60); if one ever overflows the call's output is wrong and a flag
- * is set that ms_device_status() reports.  Calls on different streams may run
- * concurrently; calls on one stream run in order.
+ * is set that ms_device_status() reports for the call's stream.  Calls on
+ * different streams may run concurrently, also from different host threads
+ * (each stream has its own scratch, status word and side streams); calls on
+ * one stream run in order.
  */
 #ifndef MERGESHUFFLE_H
 #define MERGESHUFFLE_H
@@ -183,16 +185,19 @@ uint64_t ms_scratch_bytes(uint64_t n, uint32_t elem_bytes);
  * on another implementation). */
 uint32_t ms_leaf_B_for(uint64_t n, uint32_t elem_bytes);
 
-/* Synchronize `stream`, then read and clear the device status flags of the
- * current device (bit 0: target pool overflow, bit 1: tail pool overflow,
- * bit 2: a placement chain of MS_CFG_PLACEMENT_R1 did not descend; bit 3: the
- * leaf kernel found two same-slot list pushes out of step order, i.e. the
- * device did not apply one wave's same-address LDS exchanges in lane order;
- * bits 2 and 3 are internal errors that mean a wrong result).
+/* Synchronize `stream`, then read and clear the status flags of the calls
+ * made on `stream` (each stream has its own word; a batched call's large
+ * arrays flag the caller's stream's word) and of the allocation-free entry
+ * point on the current device (bit 0: target pool overflow, bit 1: tail pool
+ * overflow, bit 2: a placement chain of MS_CFG_PLACEMENT_R1 did not descend;
+ * bit 3: the leaf kernel found two same-slot list pushes out of step order,
+ * i.e. the device did not apply one wave's same-address LDS exchanges in lane
+ * order; bits 2 and 3 are internal errors that mean a wrong result).
  * Returns MS_OK if clear, MS_ERR_CAPACITY if a flag was set. */
 int ms_device_status(void* stream, uint32_t* flags);
 
-/* Free every scratch buffer of the current device (synchronizes it). */
+/* Free every scratch buffer, status word and library stream of the current
+ * device (synchronizes it; no call may run concurrently). */
 int ms_release(void);
 
 /* The calling thread's last error message ("" if none). */

@@ -307,21 +307,23 @@ struct Arena {
   // joined back into this one, so that it overlaps the leaf kernel
   hipStream_t plan_st = nullptr;
   hipEvent_t plan_fork = nullptr, plan_join = nullptr;
+  // the status word of the calls made on this stream (byte 0) and a bit
+  // counter for calls without one (byte 64)
+  uint32_t* status = nullptr;
+  // batched calls on this stream spread their large arrays over these
+  // streams (default priority), forked from and joined back into this one;
+  // side_mu is held from the fork to the join
+  std::mutex side_mu;
+  bool side_init = false;
+  hipStream_t side[4] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[4] = {};
 };
 
 constexpr int kSideStreams = 4;
 
 struct DeviceCtx {
-  bool init = false;
-  uint32_t* status = nullptr;
-  unsigned long long* dummy_bits = nullptr;
   std::map<hipStream_t, Arena> arenas;
-  // batched calls spread their large arrays over these streams (default
-  // priority), forked from and joined back into the caller's stream
-  bool side_init = false;
-  hipStream_t side[kSideStreams] = {};
-  hipEvent_t fork = nullptr;
-  hipEvent_t join[kSideStreams] = {};
 };
 
 std::mutex g_mu;
@@ -339,15 +341,39 @@ int device_ctx(DeviceCtx** out) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   if (dev < 0 || dev >= 64) return fail(MS_ERR_HIP, "device %d out of range", dev);
-  DeviceCtx& d = g_dev[dev];
-  if (!d.init) {
-    HIP_TRY(hipMalloc(&d.status, 256));
-    HIP_TRY(hipMemset(d.status, 0, 256));
-    d.dummy_bits = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(d.status) + 64);
-    d.init = true;
-  }
-  *out = &d;
+  *out = &g_dev[dev];
   return MS_OK;
+}
+
+// The arena of stream st on the current device (created empty on first use)
+// with its status word allocated.
+int arena_of(hipStream_t st, Arena** out) {
+  DeviceCtx* dc;
+  int rc;
+  Arena* ar;
+  {
+    // g_mu, not the arena's own locks: a batched call holds side_mu while
+    // its waves look up the same arena
+    std::lock_guard<std::mutex> lk(g_mu);
+    if ((rc = device_ctx(&dc))) return rc;
+    ar = &dc->arenas[st];  // map nodes do not move
+    if (!ar->status) {
+      if (getenv("MS_FAIL_ALLOC")) return fail(MS_ERR_NOMEM, "status allocation refused (MS_FAIL_ALLOC)");
+      hipError_t e = hipMalloc(&ar->status, 256);
+      if (e != hipSuccess) {
+        ar->status = nullptr;
+        (void)hipGetLastError();
+        return fail(MS_ERR_NOMEM, "hipMalloc(256): %s", hipGetErrorString(e));
+      }
+      HIP_TRY(hipMemset(ar->status, 0, 256));
+    }
+  }
+  *out = ar;
+  return MS_OK;
+}
+
+unsigned long long* dummy_bits_of(const Arena& ar) {
+  return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(ar.status) + 64);
 }
 
 int ensure(void** p, size_t* have, size_t need, hipStream_t st) {
@@ -567,20 +593,16 @@ int check_args(const HostPlan& hp, const void* ptr) {
   return MS_OK;
 }
 
+// status: the word the call's kernels flag (null: the stream's own).
 int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, const ms_config* cfg,
-            unsigned long long* d_bits, bool ident) {
+            unsigned long long* d_bits, bool ident, uint32_t* status = nullptr) {
   HostPlan hp;
   int rc = make_plan(n, eb, cfg, hp);
   if (rc) return rc;
   if ((rc = check_args(hp, ptr))) return rc;
   if (n <= 1) return MS_OK;
-  DeviceCtx* dc;
   Arena* arp;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    if ((rc = device_ctx(&dc))) return rc;
-    arp = &dc->arenas[st];  // map nodes do not move
-  }
+  if ((rc = arena_of(st, &arp))) return rc;
   // the stream's scratch is this call's until its launches are queued
   std::lock_guard<std::mutex> alk(arp->mu);
   Arena& ar = *arp;
@@ -592,7 +614,7 @@ int run_one(void* ptr, uint64_t n, uint32_t eb, uint64_t seed, hipStream_t st, c
     HIP_TRY(hipEventCreateWithFlags(&ar.plan_join, hipEventDisableTiming));
   }
   return enqueue_call(hp, ptr, ar.data, ar.plan, seed, st, ar.plan_st, ar.plan_fork, ar.plan_join,
-                      d_bits ? d_bits : dc->dummy_bits, dc->status, ident, true);
+                      d_bits ? d_bits : dummy_bits_of(ar), status ? status : ar.status, ident, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -691,12 +713,10 @@ int stage_buffer(Arena& ar, size_t bytes, void** out, int* which) {
 // seeds: per-array seeds, or null for seed + array index.
 int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<uint32_t>& idx, uint64_t seed,
               const uint64_t* seeds,
-              hipStream_t st, unsigned long long* d_bits, DeviceCtx* dc) {
+              hipStream_t st, unsigned long long* d_bits) {
   Arena* arp;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    arp = &dc->arenas[st];
-  }
+  int rc0;
+  if ((rc0 = arena_of(st, &arp))) return rc0;
   std::lock_guard<std::mutex> alk(arp->mu);
   Arena& ar = *arp;
   const size_t head = offsetof(PlanArgs, lev);
@@ -785,7 +805,7 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
       HostPlan& hp = hps[i0 + j];
       const uint32_t a = idx[i0 + j];
       const uint64_t sa = seeds ? seeds[a] : seed + a;
-      unsigned long long* bits = d_bits ? d_bits + a : dc->dummy_bits;
+      unsigned long long* bits = d_bits ? d_bits + a : dummy_bits_of(ar);
       void* X = ptrs[a];
       void* Y = hp.nlev ? d + data_off[j] : X;
       void* cur = (hp.ngroup % 2 == 0) ? X : Y;
@@ -794,7 +814,7 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
       pa.key0 = (uint32_t)sa;
       pa.key1 = (uint32_t)(sa >> 32);
       pa.bits = bits;
-      pa.status = dc->status;
+      pa.status = ar.status;
       if (hp.nlev) {
         bind_plan(hp, d + plan_off[j]);
         // only the levels and passes in use are read on the device
@@ -820,7 +840,7 @@ int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<u
       la.key0 = pa.key0;
       la.key1 = pa.key1;
       la.bits = bits;
-      la.status = dc->status;
+      la.status = ar.status;
       const uint32_t lc = leaf_cls(hp);
       memcpy(h + leaf_off[lc] + (size_t)lfill[lc] * sizeof(LeafArgs), &la, sizeof la);
       reinterpret_cast<uint32_t*>(h + wpre_off[lc])[lfill[lc]] = lwg[lc];
@@ -955,46 +975,48 @@ static int run_batched(void* const* ptrs, const uint64_t* sizes, const uint32_t*
       }
     }
   }
-  DeviceCtx* dc;
+  Arena* car;  // the caller stream's arena: its side streams and status word
   {
-    std::lock_guard<std::mutex> lk(g_mu);
     int rc;
-    if ((rc = device_ctx(&dc))) return rc;
+    if ((rc = arena_of(st, &car))) return rc;
   }
-  // the largest arrays take the full path each, spread over the side
-  // streams (forked from and joined back into the caller's stream) so that
-  // they overlap one another and the waves
+  // the largest arrays take the full path each, spread over the caller
+  // stream's side streams (forked from and joined back into it) so that
+  // they overlap one another and the waves; the side streams and their
+  // events belong to this stream, and side_mu keeps another call on it from
+  // recording them in between
   const bool side = large.size() > 1 || (!large.empty() && !wave_idx.empty());
+  std::unique_lock<std::mutex> slk(car->side_mu, std::defer_lock);
   if (side) {
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (!dc->side_init) {
+    slk.lock();
+    if (!car->side_init) {
       for (int i = 0; i < kSideStreams; ++i) {
-        HIP_TRY(hipStreamCreateWithFlags(&dc->side[i], hipStreamNonBlocking));
-        HIP_TRY(hipEventCreateWithFlags(&dc->join[i], hipEventDisableTiming));
+        HIP_TRY(hipStreamCreateWithFlags(&car->side[i], hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&car->join[i], hipEventDisableTiming));
       }
-      HIP_TRY(hipEventCreateWithFlags(&dc->fork, hipEventDisableTiming));
-      dc->side_init = true;
+      HIP_TRY(hipEventCreateWithFlags(&car->fork, hipEventDisableTiming));
+      car->side_init = true;
     }
-    HIP_TRY(hipEventRecord(dc->fork, st));
-    for (int i = 0; i < kSideStreams; ++i) HIP_TRY(hipStreamWaitEvent(dc->side[i], dc->fork, 0));
+    HIP_TRY(hipEventRecord(car->fork, st));
+    for (int i = 0; i < kSideStreams; ++i) HIP_TRY(hipStreamWaitEvent(car->side[i], car->fork, 0));
   }
   int err = MS_OK;
   for (size_t i = 0; i < large.size() && err == MS_OK; ++i) {
     const uint32_t a = large[i];
     const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
-    const hipStream_t s2 = side ? dc->side[i % kSideStreams] : st;
+    const hipStream_t s2 = side ? car->side[i % kSideStreams] : st;
     err = run_one(ptrs[a], sizes[a], eb, seeds ? seeds[a] : seed + a, s2, cfg,
-                  d_bits_per_array ? d_bits_per_array + a : nullptr, false);
+                  d_bits_per_array ? d_bits_per_array + a : nullptr, false, car->status);
   }
   if (err == MS_OK && !wave_idx.empty())
-    err = run_waves(ptrs, wave_hp, wave_idx, seed, seeds, st, d_bits_per_array, dc);
+    err = run_waves(ptrs, wave_hp, wave_idx, seed, seeds, st, d_bits_per_array);
   if (side) {
     // joined even after an error, so that the caller's stream still orders
     // after whatever was launched
     const std::string msg = g_err;
     for (int i = 0; i < kSideStreams; ++i) {
-      HIP_TRY(hipEventRecord(dc->join[i], dc->side[i]));
-      HIP_TRY(hipStreamWaitEvent(st, dc->join[i], 0));
+      HIP_TRY(hipEventRecord(car->join[i], car->side[i]));
+      HIP_TRY(hipStreamWaitEvent(st, car->join[i], 0));
     }
     g_err = msg;
   }
@@ -1039,16 +1061,14 @@ uint32_t ms_leaf_B_for(uint64_t n, uint32_t elem_bytes) {
 
 int ms_device_status(void* stream, uint32_t* flags) {
   g_err.clear();
-  DeviceCtx* dc;
+  const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   int rc;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    if ((rc = device_ctx(&dc))) return rc;
-  }
-  HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  Arena* ar;
+  if ((rc = arena_of(st, &ar))) return rc;
+  HIP_TRY(hipStreamSynchronize(st));
   uint32_t v = 0, w = 0;
-  HIP_TRY(hipMemcpy(&v, dc->status, 4, hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemset(dc->status, 0, 4));
+  HIP_TRY(hipMemcpy(&v, ar->status, 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(ar->status, 0, 4));
   // the allocation-free calls' flags, if that entry point has run on this device
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -1085,6 +1105,14 @@ int ms_release(void) {
     if (ar.plan_fork) HIP_TRY(hipEventDestroy(ar.plan_fork));
     if (ar.plan_join) HIP_TRY(hipEventDestroy(ar.plan_join));
     if (ar.plan_st) HIP_TRY(hipStreamDestroy(ar.plan_st));
+    if (ar.status) HIP_TRY(hipFree(ar.status));
+    if (ar.side_init) {
+      for (int i = 0; i < kSideStreams; ++i) {
+        HIP_TRY(hipStreamDestroy(ar.side[i]));
+        HIP_TRY(hipEventDestroy(ar.join[i]));
+      }
+      HIP_TRY(hipEventDestroy(ar.fork));
+    }
   }
   d.arenas.clear();
   return MS_OK;

@@ -119,3 +119,53 @@ def test_full_path_arrays_beside_waves(M):
     ebs = [4, 4, 8, 16, 4, 4]
     _say("[gpu] batched full path + wave")
     _check(M, sizes, ebs, 4242)
+
+
+def test_two_host_threads_on_two_streams(M):
+    # two host threads batch full-path arrays (spread over each caller
+    # stream's own side streams) and wave arrays at the same time, each on
+    # its own stream; every result and every stream's status stays its own
+    import threading
+
+    import torch
+
+    _say("[gpu] batched from two host threads")
+    sizes = [(1 << 21) + 5, 40000, (1 << 21) + 4096, 9000, 1 << 22]
+    ebs = [4, 8, 4, 4, 8]
+    jobs = []
+    for k in range(2):
+        host, dev = _make(sizes, ebs, 900 + k)
+        jobs.append((900 + k, host, dev, torch.zeros(len(sizes), dtype=torch.int64, device="cuda"),
+                     torch.cuda.Stream()))
+    torch.cuda.synchronize()
+    errors = []
+
+    def work(seed, dev, bits, st):
+        try:
+            with torch.cuda.stream(st):
+                for _ in range(3):  # the same batch three times in a row
+                    M.shuffle_batched_(dev, seed, bits=bits, stream=st)
+            errors.append((seed, M.device_status(st)))
+        except Exception as e:  # noqa: BLE001
+            errors.append((seed, repr(e)))
+
+    th = [threading.Thread(target=work, args=(s, d, b, st)) for s, _, d, b, st in jobs]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    assert sorted(errors) == [(900, 0), (901, 0)], errors
+    for seed, host, dev, bits, _ in jobs:
+        got_bits = bits.cpu().numpy()
+        for a, (n, eb) in enumerate(zip(sizes, ebs)):
+            p, b = O.permutation(n, 4096, seed + a)
+            want = np.arange(n, dtype=np.int64)
+            for _ in range(3):
+                want = want[p.astype(np.int64)]
+            got = dev[a].cpu().numpy()
+            if eb == 4:
+                assert np.array_equal(got.view(np.uint32), want), (seed, a, n)
+            else:
+                assert np.array_equal(got, host[a][want]), (seed, a, n, eb)
+            assert got_bits[a] == 3 * b, (seed, a, n)
