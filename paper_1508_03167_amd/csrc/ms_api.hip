@@ -252,6 +252,12 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
   pa.total_merges = merges;
   pa.total_buckets = buckets;
   pa.total_tail_wgs = wgs;
+  // MS_CAP_SCALE=f (0 < f < 1) shrinks both capacities by f: a test knob that
+  // makes the overflow path (clamped writes, a status flag) reachable
+  if (const char* e = getenv("MS_CAP_SCALE")) {
+    const double f = atof(e);
+    if (f > 0.0 && f < 1.0) cap = std::max<uint64_t>(1, (uint64_t)((double)cap * f));
+  }
   pa.pool_cap = cap;
   pa.tail_cap = cap;
   hp.pass_tiles = tiles;

@@ -74,6 +74,17 @@ __device__ __forceinline__ W4 draw_block(uint32_t g, uint32_t u, uint32_t L, Key
 
 __device__ __forceinline__ int bitlen64(uint64_t x) { return 64 - __clzll(x); }
 
+// A wave-uniform value moved to a scalar register.  The builtin takes and
+// returns int: its result goes back to uint32_t here, before any widening,
+// so that a value >= 2^31 is not sign-extended into the upper half of a
+// 64-bit offset.
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ uint64_t uniform_u64(uint32_t hi, uint32_t lo) {
+  return ((uint64_t)uniform_u32(hi) << 32) | uniform_u32(lo);
+}
+
 // Fast Dice Roller in its jump form: instead of one bit at a time it reads at
 // once the d bits after which the range v first reaches k (least d with
 // v * 2^d >= k), which is the same bits in the same order with the same

@@ -178,9 +178,8 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, uint32_t tile) {
   __syncthreads();
   // the tile's length and its merge's start are the same in every lane:
   // scalar registers hold them
-  const uint32_t len = __builtin_amdgcn_readfirstlane(win[0].u1 - win[0].u0);
-  const uint64_t sM = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(win[0].s >> 32)) << 32) |
-                      __builtin_amdgcn_readfirstlane((uint32_t)win[0].s);
+  const uint32_t len = uniform_u32(win[0].u1 - win[0].u0);
+  const uint64_t sM = uniform_u64((uint32_t)(win[0].s >> 32), (uint32_t)win[0].s);
 
   // 3. loads: the 2^LAM runs of the pass input, and the first PK * NT
   //    insertion-loop patches (they land after the flips are counted)

@@ -362,11 +362,10 @@ __device__ __forceinline__ void pass_body(const GroupArgs& a, uint32_t tile) {
     for (uint32_t i = tid; i < DW4; i += NT) dst[i] = src[i];
   }
   __syncthreads();
-  const uint32_t len = __builtin_amdgcn_readfirstlane(td.len);
+  const uint32_t len = uniform_u32(td.len);
   if (len == 0) return;  // the top merge ends before this tile
-  const uint64_t sM = ((uint64_t)__builtin_amdgcn_readfirstlane(td.sM_hi) << 32) |
-                      __builtin_amdgcn_readfirstlane(td.sM_lo);
-  const uint32_t u0top = __builtin_amdgcn_readfirstlane(td.u0);
+  const uint64_t sM = uniform_u64(td.sM_hi, td.sM_lo);
+  const uint32_t u0top = uniform_u32(td.u0);
   const uint64_t sMa = a.vec_ok ? sM - sM % VE : sM;
   const E* X = reinterpret_cast<const E*>(a.X);
   const E* XM = X + sMa;
@@ -484,8 +483,8 @@ __device__ __forceinline__ void pass_body(const GroupArgs& a, uint32_t tile) {
     const R* srcR = reinterpret_cast<const R*>(src);
     R* dstR = reinterpret_cast<R*>(dst);
     // level li is depth LAM-1-li of the tree (breadth first: the top first)
-    const uint32_t e0 = __builtin_amdgcn_readfirstlane(td.dep_tb[LAM - 1 - li]);
-    const uint32_t ng = 8u * (__builtin_amdgcn_readfirstlane(td.dep_tb[LAM - li]) - e0);
+    const uint32_t e0 = uniform_u32(td.dep_tb[LAM - 1 - li]);
+    const uint32_t ng = 8u * (uniform_u32(td.dep_tb[LAM - li]) - e0);
     for (uint32_t q = tid; q < ng; q += NT) {
       const uint2 t = td.tab[e0 + (q >> 3)];
       const uint32_t G = 32u + 4u * q;
