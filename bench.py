@@ -39,7 +39,7 @@ FDR_OPS = 10.0
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("ms_kernels_data.hip", "ms_kernels_group.hip", "ms_device.hpp", "ms_plan.hpp"):
+    for f in ("ms_kernels_data.hip", "ms_kernels_group.hip", "ms_kernels_pass.hip", "ms_device.hpp", "ms_plan.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1508_03167_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -84,38 +84,75 @@ def cpu_baseline(n_log2: int):
                       f"OpenMP over the blocks and over the merges of a level"}
 
 
-def bench_batched(M, torch, reps: int = 3, count: int = 4096, seed: int = 3):
+def bench_batched(M, torch, reps: int = 5, count: int = 4096, seed: int = 3, tune: bool = True):
     """4096 uint32 arrays of log-uniform sizes in [2^8, 2^20] (seed_a = 3 + a),
-    resident in HBM: one batched call against one call per array."""
-    from paper_1508_03167_amd import inputs
+    resident in HBM: one eager batched call, the same call captured in a HIP
+    graph and replayed, the graph with autotuned knobs (cutoff, levels per
+    pass, leaf shape per size bucket), and one call per array."""
+    from paper_1508_03167_amd import autotune, inputs
 
     sizes = inputs.batched_sizes(count, seed)
     offs = np.concatenate([[0], np.cumsum(sizes)])
     total = int(offs[-1])
     buf = torch.arange(total, dtype=torch.int32, device="cuda:0")
     views = [buf[int(offs[i]):int(offs[i + 1])] for i in range(count)]
-    M.shuffle_batched_(views, seed)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        M.shuffle_batched_(views, seed)
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / reps
-    for i, v in enumerate(views):
-        M.shuffle_(v, seed + i)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        for i, v in enumerate(views):
-            M.shuffle_(v, seed + i)
-    torch.cuda.synchronize()
-    tl = (time.perf_counter() - t0) / reps
-    small = int(sum(1 for v in sizes if M.plan(int(v))["hbm_levels"] == 0))
-    return {"workload": f"{count} uint32 arrays, sizes floor(2^(8+12u)), seed {seed}+a",
-            "arrays": count, "elements": total, "arrays_in_one_workgroup": small,
-            "batched_ms": round(tb * 1e3, 3), "batched_gelem_s": round(total / tb / 1e9, 3),
-            "loop_ms": round(tl * 1e3, 3), "loop_gelem_s": round(total / tl / 1e9, 3),
-            "speedup": round(tl / tb, 3)}
+    seeds = [seed + a for a in range(count)]
+
+    def wall(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def replay(cfgs):
+        g = M.BatchGraph(views, seeds, cfgs=cfgs)
+        try:
+            g.launch()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                g.launch()
+            e1.record()
+            torch.cuda.synchronize()
+            assert g.status() == 0
+            return e0.elapsed_time(e1) / reps / 1e3, g.scratch_bytes
+        finally:
+            g.destroy()
+
+    tb = wall(lambda: M.shuffle_batched_(views, seed))
+    tg, gbytes = replay(None)
+    out = {"workload": f"{count} uint32 arrays, sizes floor(2^(8+12u)), seed {seed}+a",
+           "arrays": count, "elements": total,
+           "arrays_in_one_workgroup": int(sum(1 for v in sizes if M.plan(int(v))["hbm_levels"] == 0)),
+           "batched_ms": round(tb * 1e3, 3), "batched_gelem_s": round(total / tb / 1e9, 3),
+           "graph_replay_ms": round(tg * 1e3, 3), "graph_replay_gelem_s": round(total / tg / 1e9, 3),
+           "graph_scratch_bytes": gbytes}
+    if tune:
+        path = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"ms_tune_{os.getpid()}.json")
+        t0 = time.perf_counter()
+        rec = autotune.tune_for_batch(views, seeds, path=path, budget=1 << 22, reps=3)
+        tune_s = time.perf_counter() - t0
+        try:
+            tt, _ = replay([M.config(tuned=True)] * count)
+            out["tuned_graph_replay_ms"] = round(tt * 1e3, 3)
+            out["tuned_graph_replay_gelem_s"] = round(total / tt / 1e9, 3)
+            out["tuned_cutoffs_used"] = sorted({M.leaf_B_for(int(v)) for v in sizes})
+        finally:
+            M.tune_set([])
+        out["tuning"] = {"seconds": round(tune_s, 2), "batch": rec["batch"], "per_bucket": {
+            f"2^{e['log2_n']}": [e["leaf_B"], e["levels_per_pass"], "1024 thr" if e["leaf_big"] else "512 thr"]
+            for e in rec["entries"]}}
+    tl = wall(lambda: [M.shuffle_(v, seed + i) for i, v in enumerate(views)])
+    out.update({"loop_ms": round(tl * 1e3, 3), "loop_gelem_s": round(total / tl / 1e9, 3),
+                "speedup_batched_over_loop": round(tl / tb, 3),
+                "speedup_graph_over_loop": round(tl / tg, 3)})
+    del buf, views
+    return out
 
 
 def bench_r1(M, torch, n_log2: int = 26, seed: int = 7, reps: int = 5):
@@ -193,79 +230,60 @@ def bench_small(M, torch, n_log2: int = 20, seed: int = 1, reps: int = 200):
             "ms_by_kernel_class": {k: round(v / reps, 4) for k, v in ms.items()}}
 
 
-def bench_served(M, torch, count: int = 400, seed: int = 5, load: float = 0.7):
-    """Requests of log-uniform size in [2^10, 2^26] elements, uint32 or uint64,
-    Poisson arrivals at `load` times the measured capacity; request r uses seed
-    5 + r.  Continuous batching (every arrived request goes into the next
-    batched call) against one call per request in arrival order."""
+def bench_served(M, torch, count: int = 20000, seed: int = 5, load: float = 0.7, budget_gib: int = 32,
+                 inflight: int = 3, batch_elems: int = 1 << 21):
+    """20k requests of log-uniform size in [2^10, 2^26] elements, uint32 or
+    uint64 (random values), Poisson arrivals at `load` times the measured
+    capacity, admitted against an HBM budget (payload + library scratch) and
+    served by the continuous-batching server: the admitted requests go, in
+    arrival order, into the next batched call on a free stream (up to
+    `inflight` batches on the device; a batch closes before it would exceed
+    `batch_elems` elements, so a large request goes alone).  The same stream
+    through the plain loop: one ms_shuffle call per request, one at a time,
+    same admission.  Capacity is the throughput of the first 2000 requests all
+    present at the start, after a warm-up on the first 300."""
     from paper_1508_03167_amd import inputs
+    from paper_1508_03167_amd.serve import GpuExecutor, Request, serve_stream
 
-    reqs = inputs.served_requests(count, seed, rate_per_s=1.0)
-    nbytes = [r["n"] * r["elem_bytes"] for r in reqs]
-    offs = np.concatenate([[0], np.cumsum([(b + 255) // 256 * 256 for b in nbytes])])
-    pool = torch.randint(0, 255, (int(offs[-1]),), dtype=torch.uint8, device="cuda:0")
-    tens = []
-    for i, r in enumerate(reqs):
-        v = pool[int(offs[i]):int(offs[i]) + nbytes[i]]
-        tens.append(v.view(torch.int64 if r["elem_bytes"] == 8 else torch.int32))
-    total = sum(r["n"] for r in reqs)
-    # capacity: every request back to back in one batched call
-    M.shuffle_batched_(tens, seed)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    M.shuffle_batched_(tens, seed)
-    torch.cuda.synchronize()
-    cap = count / (time.perf_counter() - t0)
-    rate = load * cap
-    gaps = inputs.rng(seed + 1).exponential(1.0 / rate, size=count)
-    arrival = np.cumsum(gaps) - gaps[0]
+    spec = inputs.served_requests(count, seed, rate_per_s=1.0)
+    budget = budget_gib << 30
+    mean_n = float(np.mean([d["n"] for d in spec]))
 
-    def serve(batched: bool):
-        lat = np.zeros(count)
-        nxt = 0
-        start = time.perf_counter()
-        while nxt < count:
-            now = time.perf_counter() - start
-            if arrival[nxt] > now:
-                time.sleep(min(arrival[nxt] - now, 0.001))
-                continue
-            last = nxt + 1
-            if batched:
-                while last < count and arrival[last] <= now:
-                    last += 1
-                M.shuffle_batched_(tens[nxt:last], seed + nxt)
-            else:
-                M.shuffle_(tens[nxt], seed + nxt)
-            torch.cuda.synchronize()
-            done = time.perf_counter() - start
-            lat[nxt:last] = done - arrival[nxt:last]
-            nxt = last
-        return lat, time.perf_counter() - start
+    def fill(pool):
+        g = torch.Generator(device="cuda:0")
+        g.manual_seed(seed)
+        pool.random_(0, 256, generator=g)
 
-    check = [0, count // 2, count - 1]
-    before = {i: tens[i].clone() for i in check}
-    torch.cuda.synchronize()
-    lat_b, span_b = serve(True)
-    # a request's result is the same alone as in a batch
-    same = True
-    for i in check:
-        y = before[i].clone()
-        M.shuffle_(y, seed + i)
-        torch.cuda.synchronize()
-        same = same and bool(torch.equal(tens[i], y))
-    lat_l, span_l = serve(False)
+    def requests(rate, k=count):
+        return [Request(i, d["n"], d["elem_bytes"], d["seed"], d["arrival_s"] / rate if rate else 0.0)
+                for i, d in enumerate(spec[:k])]
 
-    def q(a, p):
-        return round(float(np.percentile(a, p)) * 1e3, 3)
+    def run(rate, k, batched, check=()):
+        ex = GpuExecutor(budget, inflight if batched else 1, fill=fill, batched=batched, check=check)
+        if batched:
+            r = serve_stream(requests(rate, k), ex, budget, inflight, max_batch_elems=batch_elems)
+        else:
+            r = serve_stream(requests(rate, k), ex, budget, max_inflight=1, max_batch=1)
+        if check:
+            r["results_checked_alone"] = len(ex.checked)
+            r["results_equal_alone_and_in_mix"] = not ex.mismatches and len(ex.checked) == len(check)
+        del ex
+        torch.cuda.empty_cache()
+        return r
 
-    return {"workload": f"{count} requests, sizes floor(2^(10+16u)), uint32 or uint64, Poisson arrivals at "
-                        f"{load} x capacity, seed {seed}+r",
-            "requests": count, "elements": int(total), "capacity_req_s": round(cap, 1),
+    run(None, 300, True)
+    cap = run(None, 2000, True)
+    cap_plain = run(None, 2000, False)
+    rate = load * cap["gelem_s"] * 1e9 / mean_n
+    batched = run(rate, count, True, check=set(range(0, count, count // 16)))
+    plain = run(rate, count, False)
+    return {"workload": f"{count} requests, sizes floor(2^(10+16u)), uint32 or uint64 random values, "
+                        f"Poisson arrivals at {load} x measured capacity, HBM budget {budget_gib} GiB, seed {seed}",
+            "requests": count, "mean_elements": round(mean_n), "inflight_batches": inflight,
+            "batch_elems_cap": batch_elems,
+            "capacity_gelem_s": {"continuous_batching": cap["gelem_s"], "one_call_per_request": cap_plain["gelem_s"]},
             "arrival_rate_req_s": round(rate, 1),
-            "batched": {"p50_ms": q(lat_b, 50), "p99_ms": q(lat_b, 99), "gelem_s": round(total / span_b / 1e9, 3)},
-            "one_call_per_request": {"p50_ms": q(lat_l, 50), "p99_ms": q(lat_l, 99),
-                                     "gelem_s": round(total / span_l / 1e9, 3)},
-            "results_equal_alone_and_in_batch": same}
+            "continuous_batching": batched, "one_call_per_request": plain}
 
 
 def main():

@@ -101,6 +101,15 @@ typedef struct ms_config {
 #define MS_CFG_HBM_ONLY 1u
 #define MS_CFG_ONE_LEVEL_PASSES 2u
 #define MS_CFG_PLACEMENT_R1 4u
+/* MS_CFG_LEAF_BIG: run the leaves in 128 KiB super-blocks of 1024 threads
+ * (the default is 64 KiB and 512 threads): a workgroup shape, the permutation
+ * does not depend on it. */
+#define MS_CFG_LEAF_BIG 8u
+/* MS_CFG_TUNED: take leaf_B, levels_per_pass and MS_CFG_LEAF_BIG from the
+ * tuning table entry of the call's (elem_bytes, floor(log2 n)), if there is
+ * one (see ms_tune_set); the other fields as given.  The tuned cutoff changes
+ * the permutation like any cutoff: ms_leaf_B_for reports it. */
+#define MS_CFG_TUNED 16u
 
 /* Shuffle n elements of elem_bytes bytes at dev_ptr in place (Algorithm
  * MergeShuffle with cutoff 4096), seed as above, on stream. */
@@ -163,6 +172,35 @@ int ms_shuffle_batched_seeds(void* const* ptrs, const uint64_t* sizes, const uin
                              const uint64_t* seeds, uint32_t count, void* stream, const ms_config* cfg,
                              unsigned long long* d_bits_per_array);
 
+/* A batched call captured once in a HIP graph and replayed: for callers
+ * that shuffle the same set of device arrays again and again (an epoch loop
+ * over fixed buffers).  ms_batch_graph_create plans every array (array a with
+ * sizes[a] elements of elem_bytes[a] bytes (NULL: 4), seed seeds[a] and the
+ * knobs cfgs[a] (NULL: defaults), as ms_shuffle_ex would), allocates the
+ * graph's own scratch (every wave's plan tables and array copies, the
+ * full-path arrays' plan tables and copies, a status word; about
+ * ms_batch_graph_bytes), writes the launch descriptors to the device once and
+ * captures the launch sequence of ms_shuffle_batched_seeds into a graph:
+ * kernel launches only, no host work and no memset nodes.  Nothing runs at
+ * creation.  Each ms_batch_graph_launch then shuffles every array in place on
+ * `stream` exactly as ms_shuffle_ex(ptrs[a], sizes[a], elem_bytes[a],
+ * seeds[a], stream, &cfgs[a], ...) would (the k-th launch leaves the k-fold
+ * permutation), adding the bits to d_bits_per_array (device, count counters,
+ * or NULL).  The arrays must stay allocated while the graph lives.  Launches
+ * of one graph must not overlap in time (they share its scratch): launch it on
+ * one stream, or order the streams.  ms_batch_graph_status synchronizes
+ * `stream`, then reads and clears the graph's status word (as
+ * ms_device_status).  ms_batch_graph_destroy synchronizes the device and
+ * frees everything the graph holds. */
+typedef struct ms_batch_graph ms_batch_graph;
+int ms_batch_graph_create(void* const* ptrs, const uint64_t* sizes, const uint32_t* elem_bytes,
+                          const uint64_t* seeds, uint32_t count, const ms_config* cfgs,
+                          unsigned long long* d_bits_per_array, ms_batch_graph** out);
+int ms_batch_graph_launch(ms_batch_graph* g, void* stream);
+int ms_batch_graph_status(ms_batch_graph* g, void* stream, uint32_t* flags);
+uint64_t ms_batch_graph_bytes(const ms_batch_graph* g);
+int ms_batch_graph_destroy(ms_batch_graph* g);
+
 /* Plan of one call, computed on the host (no GPU needed). */
 typedef struct ms_plan_info {
   uint32_t levels;        /* c */
@@ -181,8 +219,25 @@ int ms_plan(uint64_t n, uint32_t elem_bytes, const ms_config* cfg, ms_plan_info*
 /* Library scratch a call of this size needs, in bytes (0 if unsupported). */
 uint64_t ms_scratch_bytes(uint64_t n, uint32_t elem_bytes);
 
-/* The cutoff the library uses for a call of this size (for replaying a call
- * on another implementation). */
+/* Tuning table (process-wide, all devices): one entry per element size and
+ * size bucket [2^log2_n, 2^(log2_n+1)), as an autotuner measured them.
+ * ms_tune_set replaces the whole table (count 0 clears it); it returns
+ * MS_ERR_INVALID, and keeps the old table, if an entry has an element size
+ * other than 4/8/16, log2_n above 32, a cutoff outside 1..4096, more than 4
+ * levels per pass or a flag other than MS_CFG_LEAF_BIG.  Calls with
+ * MS_CFG_TUNED read it when they are planned. */
+typedef struct ms_tune_entry {
+  uint32_t elem_bytes;
+  uint32_t log2_n;
+  uint32_t leaf_B;          /* cutoff */
+  uint32_t levels_per_pass; /* 0 = default */
+  uint32_t flags;           /* 0 or MS_CFG_LEAF_BIG */
+} ms_tune_entry;
+int ms_tune_set(const ms_tune_entry* entries, uint32_t count);
+
+/* The cutoff a call of this size with MS_CFG_TUNED uses: the tuning table's
+ * entry for its bucket, else the default 4096 (for replaying a call on
+ * another implementation, such as a CPU reference). */
 uint32_t ms_leaf_B_for(uint64_t n, uint32_t elem_bytes);
 
 /* Synchronize `stream`, then read and clear the status flags of the calls

@@ -126,7 +126,39 @@ uint64_t ceil_shift(uint64_t n, uint32_t s) { return (n + (1ull << s) - 1) >> s;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// ---------------------------------------------------------------------------
+// tuning table: per (element size, floor(log2 n)) the cutoff, the fused
+// levels per pass and the leaf shape that calls with MS_CFG_TUNED take
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<uint64_t, ms_tune_entry> g_tune;
+
+uint64_t tune_key(uint32_t eb, uint64_t n) {
+  uint32_t k = 0;
+  while (k < 63 && (n >> (k + 1)) != 0) ++k;
+  return ((uint64_t)eb << 32) | k;
+}
+
+bool tune_lookup(uint64_t n, uint32_t eb, ms_tune_entry* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(tune_key(eb, n));
+  if (it == g_tune.end()) return false;
+  *out = it->second;
+  return true;
+}
+
 int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
+  ms_config tuned;
+  if (cfg && (cfg->flags & MS_CFG_TUNED)) {
+    tuned = *cfg;
+    ms_tune_entry e;
+    if (tune_lookup(n, eb, &e)) {
+      tuned.leaf_B = e.leaf_B;
+      tuned.levels_per_pass = e.levels_per_pass;
+      tuned.flags = (tuned.flags & ~MS_CFG_LEAF_BIG) | (e.flags & MS_CFG_LEAF_BIG);
+    }
+    cfg = &tuned;
+  }
   if (eb != 4 && eb != 8 && eb != 16) return fail(MS_ERR_UNSUPPORTED, "element size %u not in {4,8,16}", eb);
   if (n > kMaxN) return fail(MS_ERR_UNSUPPORTED, "n = %llu exceeds %llu", (unsigned long long)n,
                              (unsigned long long)kMaxN);
@@ -142,7 +174,8 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
   hp.q = 1ull << c;
   // the default super-block, or the 128 KiB one when a leaf does not fit
   // (16-byte leaves of cutoff + 1 = 4097 records)
-  hp.leaf_big = leaf_big_default() || ceil_shift(n, c) > (uint64_t)leaf_capacity(eb, false);
+  hp.leaf_big = leaf_big_default() || (cfg && (cfg->flags & MS_CFG_LEAF_BIG)) ||
+                ceil_shift(n, c) > (uint64_t)leaf_capacity(eb, false);
   const uint64_t scap = (uint64_t)leaf_capacity(eb, hp.leaf_big);
   if (ceil_shift(n, c) > scap) return fail(MS_ERR_UNSUPPORTED, "leaf of %llu elements does not fit in LDS",
                                            (unsigned long long)ceil_shift(n, c));
@@ -716,192 +749,376 @@ int stage_buffer(Arena& ar, size_t bytes, void** out, int* which) {
   return MS_OK;
 }
 
+// One wave of a batched call: arrays hps[i0 .. i1) with one device region
+// holding, in order, the launch descriptors (plan arguments, unit prefixes,
+// leaf and fused-pass arguments with their workgroup prefixes), then each
+// array's plan tables, then each array's copy.
+constexpr int kUnits = 5;    // plan stages launched per array
+constexpr int kLeafCls = 6;  // leaf launch classes: element size x super-block size
+struct GSec {
+  size_t off = 0, tpre_off = 0;
+  uint32_t n = 0, fill = 0, tiles = 0;
+};
+struct WaveLayout {
+  size_t i0 = 0, i1 = 0;
+  uint32_t np = 0;
+  uint32_t nleaf[kLeafCls] = {0, 0, 0, 0, 0, 0};
+  size_t pa_off = 0, pre_off[kUnits] = {}, leaf_off[kLeafCls] = {}, wpre_off[kLeafCls] = {};
+  std::map<uint32_t, GSec> gsec;  // key (g * 3 + cls) * 4 + lam - 1, ordered by pass
+  std::vector<size_t> plan_off, data_off;
+  size_t desc_bytes = 0, bytes = 0;
+  // set by wave_fill
+  uint32_t units[kUnits] = {0, 0, 0, 0, 0};
+  uint32_t lwg[kLeafCls] = {0, 0, 0, 0, 0, 0};
+};
+
+uint32_t cls_of(uint32_t eb) { return eb == 4 ? 0u : eb == 8 ? 1u : 2u; }
+uint32_t leaf_cls(const HostPlan& hp) { return cls_of(hp.eb) * 2 + (hp.leaf_big ? 1u : 0u); }
+uint32_t eb_of_cls(uint32_t cls) { return cls == 0 ? 4u : cls == 1 ? 8u : 16u; }
+
+// The arrays of the wave that starts at i0 (at most wmax arrays and
+// kWaveScratch bytes of plans and copies, at least one array).
+size_t wave_end(const std::vector<HostPlan>& hps, size_t i0, uint32_t wmax) {
+  size_t i1 = i0, scratch = 0;
+  while (i1 < hps.size() && i1 - i0 < wmax) {
+    const HostPlan& hp = hps[i1];
+    const size_t need = hp.nlev ? align256(hp.lay.bytes) + align256(hp.n * hp.eb) : 0;
+    if (i1 > i0 && scratch + need > kWaveScratch) break;
+    scratch += need;
+    ++i1;
+  }
+  return i1;
+}
+
+void wave_layout(const std::vector<HostPlan>& hps, size_t i0, size_t i1, WaveLayout& w) {
+  w.i0 = i0;
+  w.i1 = i1;
+  std::map<uint32_t, uint32_t> gcount;
+  for (size_t i = i0; i < i1; ++i) {
+    const HostPlan& hp = hps[i];
+    ++w.nleaf[leaf_cls(hp)];
+    if (hp.nlev) ++w.np;
+    for (uint32_t g = 0; g < hp.ngroup; ++g) ++gcount[(g * 3 + cls_of(hp.eb)) * 4 + hp.glam[g] - 1];
+  }
+  size_t o = 0;
+  w.pa_off = o;
+  o += align256((size_t)w.np * sizeof(PlanArgs));
+  for (int k = 0; k < kUnits; ++k) {
+    w.pre_off[k] = o;
+    o += align256(((size_t)w.np + 1) * 4);
+  }
+  for (int c = 0; c < kLeafCls; ++c) {
+    w.leaf_off[c] = o;
+    o += align256((size_t)w.nleaf[c] * sizeof(LeafArgs));
+    w.wpre_off[c] = o;
+    o += align256(((size_t)w.nleaf[c] + 1) * 4);
+  }
+  for (const auto& kv : gcount) {
+    GSec sc;
+    sc.off = o;
+    o += align256((size_t)kv.second * sizeof(GroupArgs));
+    sc.tpre_off = o;
+    o += align256(((size_t)kv.second + 1) * 4);
+    sc.n = kv.second;
+    w.gsec[kv.first] = sc;
+  }
+  w.desc_bytes = o;
+  const size_t nw = i1 - i0;
+  w.plan_off.assign(nw, 0);
+  w.data_off.assign(nw, 0);
+  for (size_t j = 0; j < nw; ++j) {
+    if (!hps[i0 + j].nlev) continue;
+    w.plan_off[j] = o;
+    o += align256(hps[i0 + j].lay.bytes);
+  }
+  for (size_t j = 0; j < nw; ++j) {
+    if (!hps[i0 + j].nlev) continue;
+    w.data_off[j] = o;
+    o += align256(hps[i0 + j].n * hps[i0 + j].eb);
+  }
+  w.bytes = o;
+}
+
+// Write the wave's descriptors to h (desc_bytes bytes, to be copied to the
+// start of the device region d).  Array a = idx[i] uses seeds[a] (or seed +
+// a), counts its bits in d_bits[a] (or `spare`) and flags `status`.
+void wave_fill(std::vector<HostPlan>& hps, const std::vector<uint32_t>& idx, WaveLayout& w, char* h, char* d,
+               void* const* ptrs, uint64_t seed, const uint64_t* seeds, unsigned long long* d_bits,
+               unsigned long long* spare, uint32_t* status) {
+  const size_t head = offsetof(PlanArgs, lev);
+  uint32_t pfill = 0, lfill[kLeafCls] = {0, 0, 0, 0, 0, 0};
+  for (auto& kv : w.gsec) kv.second.fill = kv.second.tiles = 0;
+  for (int k = 0; k < kUnits; ++k) w.units[k] = 0;
+  for (int c = 0; c < kLeafCls; ++c) w.lwg[c] = 0;
+  for (size_t j = 0; j < w.i1 - w.i0; ++j) {
+    HostPlan& hp = hps[w.i0 + j];
+    const uint32_t a = idx[w.i0 + j];
+    const uint64_t sa = seeds ? seeds[a] : seed + a;
+    unsigned long long* bits = d_bits ? d_bits + a : spare;
+    void* X = ptrs[a];
+    void* Y = hp.nlev ? d + w.data_off[j] : X;
+    void* cur = (hp.ngroup % 2 == 0) ? X : Y;
+    PlanArgs& pa = hp.pa;
+    pa.key0 = (uint32_t)sa;
+    pa.key1 = (uint32_t)(sa >> 32);
+    pa.bits = bits;
+    pa.status = status;
+    if (hp.nlev) {
+      bind_plan(hp, d + w.plan_off[j]);
+      // only the levels and passes in use are read on the device
+      char* dst = h + w.pa_off + (size_t)pfill * sizeof(PlanArgs);
+      memcpy(dst, &pa, head);
+      memcpy(dst + head, pa.lev, hp.nlev * sizeof(HbmLevel));
+      memcpy(dst + offsetof(PlanArgs, grp), pa.grp, hp.ngroup * sizeof(GroupInfo));
+      const uint64_t per[kUnits] = {pa.total_chunks, (std::max(pa.total_chunks, pa.total_buckets) + 255) / 256,
+                                    (pa.total_merges + 255) / 256, pa.total_tail_wgs,
+                                    pa.total_tail_wgs + (pa.total_bnd + 255) / 256};
+      for (int k = 0; k < kUnits; ++k) {
+        reinterpret_cast<uint32_t*>(h + w.pre_off[k])[pfill] = w.units[k];
+        w.units[k] += (uint32_t)per[k];
+      }
+      ++pfill;
+    }
+    LeafArgs la;
+    la.in = X;
+    la.out = cur;
+    la.n = hp.n;
+    la.c = hp.c;
+    la.lds_levels = hp.lam;
+    la.key0 = pa.key0;
+    la.key1 = pa.key1;
+    la.bits = bits;
+    la.status = status;
+    const uint32_t lc = leaf_cls(hp);
+    memcpy(h + w.leaf_off[lc] + (size_t)lfill[lc] * sizeof(LeafArgs), &la, sizeof la);
+    reinterpret_cast<uint32_t*>(h + w.wpre_off[lc])[lfill[lc]] = w.lwg[lc];
+    ++lfill[lc];
+    w.lwg[lc] += (uint32_t)(hp.q >> hp.lam);
+    for (uint32_t g = 0; g < hp.ngroup; ++g) {
+      void* other = cur == X ? Y : X;
+      const GroupArgs ga = group_args(hp, g, cur, other);
+      GSec& sc = w.gsec[(g * 3 + cls_of(hp.eb)) * 4 + hp.glam[g] - 1];
+      memcpy(h + sc.off + (size_t)sc.fill * sizeof(GroupArgs), &ga, sizeof ga);
+      reinterpret_cast<uint32_t*>(h + sc.tpre_off)[sc.fill] = sc.tiles;
+      sc.tiles += ga.ntiles;
+      ++sc.fill;
+      cur = other;
+    }
+  }
+  for (int k = 0; k < kUnits; ++k) reinterpret_cast<uint32_t*>(h + w.pre_off[k])[w.np] = w.units[k];
+  for (int c = 0; c < kLeafCls; ++c) reinterpret_cast<uint32_t*>(h + w.wpre_off[c])[w.nleaf[c]] = w.lwg[c];
+  for (auto& kv : w.gsec) reinterpret_cast<uint32_t*>(h + kv.second.tpre_off)[kv.second.n] = kv.second.tiles;
+}
+
+// The wave's launches on st, reading the descriptors at d: the plan stages
+// and the pass descriptors of every array, the leaf kernels, the passes.
+int wave_launch(const WaveLayout& w, char* d, hipStream_t st, bool prof) {
+  if (w.np) {
+    const uint32_t* pre[kUnits];
+    for (int k = 0; k < kUnits; ++k) pre[k] = reinterpret_cast<const uint32_t*>(d + w.pre_off[k]);
+    ProfScope ps(prof ? 0 : -1, st);
+    launch_plan_multi(reinterpret_cast<const PlanArgs*>(d + w.pa_off), w.np, pre, w.units, st);
+    if (!pass_tree()) {
+      for (const auto& kv : w.gsec) {
+        const uint32_t key = kv.first;
+        const uint32_t lam = key % 4 + 1, cls = (key / 4) % 3;
+        launch_pass_desc_multi(reinterpret_cast<const GroupArgs*>(d + kv.second.off),
+                               reinterpret_cast<const uint32_t*>(d + kv.second.tpre_off), kv.second.n,
+                               kv.second.tiles, (int)lam, eb_of_cls(cls), st);
+      }
+    }
+  }
+  for (int c = 0; c < kLeafCls; ++c) {
+    if (!w.nleaf[c]) continue;
+    ProfScope ps(prof ? 1 : -1, st);
+    launch_leaf_multi(reinterpret_cast<const LeafArgs*>(d + w.leaf_off[c]),
+                      reinterpret_cast<const uint32_t*>(d + w.wpre_off[c]), w.nleaf[c], w.lwg[c],
+                      eb_of_cls((uint32_t)c / 2), (c & 1) != 0, st);
+  }
+  for (const auto& kv : w.gsec) {
+    const uint32_t key = kv.first;
+    const uint32_t lam = key % 4 + 1, cls = (key / 4) % 3;
+    ProfScope ps(prof ? 2 : -1, st);
+    launch_fused_multi(reinterpret_cast<const GroupArgs*>(d + kv.second.off),
+                       reinterpret_cast<const uint32_t*>(d + kv.second.tpre_off), kv.second.n, kv.second.tiles,
+                       (int)lam, eb_of_cls(cls), st);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MS_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
+  return MS_OK;
+}
+
+// The waves of a batched call on st: each wave's descriptors go through a
+// pinned staging buffer into the stream's wave region, then its launches.
 // seeds: per-array seeds, or null for seed + array index.
 int run_waves(void* const* ptrs, std::vector<HostPlan>& hps, const std::vector<uint32_t>& idx, uint64_t seed,
-              const uint64_t* seeds,
-              hipStream_t st, unsigned long long* d_bits) {
+              const uint64_t* seeds, hipStream_t st, unsigned long long* d_bits) {
   Arena* arp;
   int rc0;
   if ((rc0 = arena_of(st, &arp))) return rc0;
   std::lock_guard<std::mutex> alk(arp->mu);
   Arena& ar = *arp;
-  const size_t head = offsetof(PlanArgs, lev);
   const uint32_t wmax = wave_max_arrays();
-  auto cls_of = [](uint32_t eb) { return eb == 4 ? 0u : eb == 8 ? 1u : 2u; };
-  // leaf launch classes: element size x super-block size
-  constexpr int kLeafCls = 6;
-  auto leaf_cls = [&](const HostPlan& hp) { return cls_of(hp.eb) * 2 + (hp.leaf_big ? 1u : 0u); };
   size_t i0 = 0;
   while (i0 < idx.size()) {
-    // the wave: arrays idx[i0 .. i1)
-    size_t i1 = i0, scratch = 0;
-    while (i1 < idx.size() && i1 - i0 < wmax) {
-      const HostPlan& hp = hps[i1];
-      const size_t need = hp.nlev ? align256(hp.lay.bytes) + align256(hp.n * hp.eb) : 0;
-      if (i1 > i0 && scratch + need > kWaveScratch) break;
-      scratch += need;
-      ++i1;
-    }
-    const uint32_t nw = (uint32_t)(i1 - i0);
-    // launch classes: plan jobs (arrays with HBM passes), leaves per element
-    // size, fused pass g per (g, element size, levels)
-    uint32_t np = 0, nleaf[kLeafCls] = {0, 0, 0, 0, 0, 0};
-    std::map<uint32_t, uint32_t> gcount;  // key (g * 3 + cls) * 4 + lam - 1, ordered by pass
-    for (size_t i = i0; i < i1; ++i) {
-      const HostPlan& hp = hps[i];
-      const uint32_t cls = cls_of(hp.eb);
-      ++nleaf[leaf_cls(hp)];
-      if (hp.nlev) ++np;
-      for (uint32_t g = 0; g < hp.ngroup; ++g) ++gcount[(g * 3 + cls) * 4 + hp.glam[g] - 1];
-    }
-    size_t o = 0;
-    const size_t pa_off = o;
-    o += align256((size_t)np * sizeof(PlanArgs));
-    constexpr int kUnits = 5;
-    size_t pre_off[kUnits];
-    for (int k = 0; k < kUnits; ++k) {
-      pre_off[k] = o;
-      o += align256(((size_t)np + 1) * 4);
-    }
-    size_t leaf_off[kLeafCls], wpre_off[kLeafCls];
-    for (int c = 0; c < kLeafCls; ++c) {
-      leaf_off[c] = o;
-      o += align256((size_t)nleaf[c] * sizeof(LeafArgs));
-      wpre_off[c] = o;
-      o += align256(((size_t)nleaf[c] + 1) * 4);
-    }
-    struct GSec {
-      size_t off, tpre_off;
-      uint32_t n, fill, tiles;
-    };
-    std::map<uint32_t, GSec> gsec;
-    for (const auto& kv : gcount) {
-      GSec sc;
-      sc.off = o;
-      o += align256((size_t)kv.second * sizeof(GroupArgs));
-      sc.tpre_off = o;
-      o += align256(((size_t)kv.second + 1) * 4);
-      sc.n = kv.second;
-      sc.fill = 0;
-      sc.tiles = 0;
-      gsec[kv.first] = sc;
-    }
-    const size_t desc_bytes = o;
-    std::vector<size_t> plan_off(nw, 0), data_off(nw, 0);
-    for (uint32_t j = 0; j < nw; ++j) {
-      if (!hps[i0 + j].nlev) continue;
-      plan_off[j] = o;
-      o += align256(hps[i0 + j].lay.bytes);
-    }
-    for (uint32_t j = 0; j < nw; ++j) {
-      if (!hps[i0 + j].nlev) continue;
-      data_off[j] = o;
-      o += align256(hps[i0 + j].n * hps[i0 + j].eb);
-    }
+    WaveLayout w;
+    wave_layout(hps, i0, wave_end(hps, i0, wmax), w);
     int rc;
-    if ((rc = ensure(&ar.wave, &ar.wave_bytes, o, st))) return rc;
+    if ((rc = ensure(&ar.wave, &ar.wave_bytes, w.bytes, st))) return rc;
     void* stg = nullptr;
     int si = 0;
-    if ((rc = stage_buffer(ar, desc_bytes, &stg, &si))) return rc;
+    if ((rc = stage_buffer(ar, w.desc_bytes, &stg, &si))) return rc;
     char* h = reinterpret_cast<char*>(stg);
     char* d = reinterpret_cast<char*>(ar.wave);
-    uint32_t pfill = 0, units[kUnits] = {0, 0, 0, 0, 0};
-    uint32_t lfill[kLeafCls] = {0, 0, 0, 0, 0, 0}, lwg[kLeafCls] = {0, 0, 0, 0, 0, 0};
-    for (uint32_t j = 0; j < nw; ++j) {
-      HostPlan& hp = hps[i0 + j];
-      const uint32_t a = idx[i0 + j];
-      const uint64_t sa = seeds ? seeds[a] : seed + a;
-      unsigned long long* bits = d_bits ? d_bits + a : dummy_bits_of(ar);
-      void* X = ptrs[a];
-      void* Y = hp.nlev ? d + data_off[j] : X;
-      void* cur = (hp.ngroup % 2 == 0) ? X : Y;
-      const uint32_t cls = cls_of(hp.eb);
-      PlanArgs& pa = hp.pa;
-      pa.key0 = (uint32_t)sa;
-      pa.key1 = (uint32_t)(sa >> 32);
-      pa.bits = bits;
-      pa.status = ar.status;
-      if (hp.nlev) {
-        bind_plan(hp, d + plan_off[j]);
-        // only the levels and passes in use are read on the device
-        char* dst = h + pa_off + (size_t)pfill * sizeof(PlanArgs);
-        memcpy(dst, &pa, head);
-        memcpy(dst + head, pa.lev, hp.nlev * sizeof(HbmLevel));
-        memcpy(dst + offsetof(PlanArgs, grp), pa.grp, hp.ngroup * sizeof(GroupInfo));
-        const uint64_t per[kUnits] = {pa.total_chunks, (std::max(pa.total_chunks, pa.total_buckets) + 255) / 256,
-                                      (pa.total_merges + 255) / 256, pa.total_tail_wgs,
-                                      pa.total_tail_wgs + (pa.total_bnd + 255) / 256};
-        for (int k = 0; k < kUnits; ++k) {
-          reinterpret_cast<uint32_t*>(h + pre_off[k])[pfill] = units[k];
-          units[k] += (uint32_t)per[k];
-        }
-        ++pfill;
-      }
-      LeafArgs la;
-      la.in = X;
-      la.out = cur;
-      la.n = hp.n;
-      la.c = hp.c;
-      la.lds_levels = hp.lam;
-      la.key0 = pa.key0;
-      la.key1 = pa.key1;
-      la.bits = bits;
-      la.status = ar.status;
-      const uint32_t lc = leaf_cls(hp);
-      memcpy(h + leaf_off[lc] + (size_t)lfill[lc] * sizeof(LeafArgs), &la, sizeof la);
-      reinterpret_cast<uint32_t*>(h + wpre_off[lc])[lfill[lc]] = lwg[lc];
-      ++lfill[lc];
-      lwg[lc] += (uint32_t)(hp.q >> hp.lam);
-      for (uint32_t g = 0; g < hp.ngroup; ++g) {
-        void* other = cur == X ? Y : X;
-        const GroupArgs ga = group_args(hp, g, cur, other);
-        GSec& sc = gsec[(g * 3 + cls) * 4 + hp.glam[g] - 1];
-        memcpy(h + sc.off + (size_t)sc.fill * sizeof(GroupArgs), &ga, sizeof ga);
-        reinterpret_cast<uint32_t*>(h + sc.tpre_off)[sc.fill] = sc.tiles;
-        sc.tiles += ga.ntiles;
-        ++sc.fill;
-        cur = other;
-      }
-    }
-    for (int k = 0; k < kUnits; ++k) reinterpret_cast<uint32_t*>(h + pre_off[k])[np] = units[k];
-    for (int c = 0; c < kLeafCls; ++c) reinterpret_cast<uint32_t*>(h + wpre_off[c])[nleaf[c]] = lwg[c];
-    for (auto& kv : gsec) reinterpret_cast<uint32_t*>(h + kv.second.tpre_off)[kv.second.n] = kv.second.tiles;
-    HIP_TRY(hipMemcpyAsync(d, h, desc_bytes, hipMemcpyHostToDevice, st));
+    wave_fill(hps, idx, w, h, d, ptrs, seed, seeds, d_bits, dummy_bits_of(ar), ar.status);
+    HIP_TRY(hipMemcpyAsync(d, h, w.desc_bytes, hipMemcpyHostToDevice, st));
     HIP_TRY(hipEventRecord(ar.stage_done[si], st));
-    if (np) {
-      const uint32_t* pre[kUnits];
-      for (int k = 0; k < kUnits; ++k) pre[k] = reinterpret_cast<const uint32_t*>(d + pre_off[k]);
-      ProfScope ps(0, st);
-      launch_plan_multi(reinterpret_cast<const PlanArgs*>(d + pa_off), np, pre, units, st);
-      if (!pass_tree()) {
-        for (auto& kv : gsec) {
-          const uint32_t key = kv.first;
-          const uint32_t lam = key % 4 + 1, cls = (key / 4) % 3;
-          launch_pass_desc_multi(reinterpret_cast<const GroupArgs*>(d + kv.second.off),
-                                 reinterpret_cast<const uint32_t*>(d + kv.second.tpre_off), kv.second.n,
-                                 kv.second.tiles, (int)lam, cls == 0 ? 4u : cls == 1 ? 8u : 16u, st);
-        }
+    if ((rc = wave_launch(w, d, st, true))) return rc;
+    i0 = w.i1;
+  }
+  return MS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched calls captured once in a HIP graph and replayed
+// ---------------------------------------------------------------------------
+// The graph owns every buffer its kernels touch besides the arrays: each
+// wave's region (descriptors written once, at creation), each full-path
+// array's plan tables and copy, and a status word.  Its nodes are kernel
+// launches only (every clear is done by a kernel) and the event edges of
+// the side streams the full-path arrays run on.
+struct BatchGraph {
+  int device = 0;
+  std::vector<void*> bufs;
+  uint32_t* status = nullptr;  // status word (byte 0), spare bit counter (byte 64)
+  hipStream_t cap = nullptr;
+  hipStream_t side[kSideStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kSideStreams] = {};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t bytes = 0;
+};
+
+void graph_free(BatchGraph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  for (void* b : g->bufs) (void)hipFree(b);
+  if (g->status) (void)hipFree(g->status);
+  for (int i = 0; i < kSideStreams; ++i) {
+    if (g->side[i]) (void)hipStreamDestroy(g->side[i]);
+    if (g->join[i]) (void)hipEventDestroy(g->join[i]);
+  }
+  if (g->fork) (void)hipEventDestroy(g->fork);
+  if (g->cap) (void)hipStreamDestroy(g->cap);
+  delete g;
+}
+
+int graph_alloc(BatchGraph* g, size_t bytes, void** out) {
+  *out = nullptr;
+  if (!bytes) return MS_OK;
+  if (getenv("MS_FAIL_ALLOC")) return fail(MS_ERR_NOMEM, "graph scratch of %zu bytes refused (MS_FAIL_ALLOC)", bytes);
+  hipError_t e = hipMalloc(out, bytes);
+  if (e != hipSuccess) {
+    *out = nullptr;
+    (void)hipGetLastError();
+    return fail(MS_ERR_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  g->bufs.push_back(*out);
+  g->bytes += bytes;
+  return MS_OK;
+}
+
+int graph_build(BatchGraph* g, void* const* ptrs, const uint64_t* sizes, const uint32_t* elem_bytes,
+                const uint64_t* seeds, uint32_t count, const ms_config* cfgs, unsigned long long* d_bits) {
+  std::vector<uint32_t> wave_idx, large;
+  std::vector<HostPlan> wave_hp, large_hp;
+  for (uint32_t a = 0; a < count; ++a) {
+    HostPlan hp;
+    const uint32_t eb = elem_bytes ? elem_bytes[a] : 4u;
+    int rc = make_plan(sizes[a], eb, cfgs ? &cfgs[a] : nullptr, hp);
+    if (rc) return fail(rc, "array %u: %s", a, g_err.c_str());
+    if (sizes[a] > 0 && !ptrs[a]) return fail(MS_ERR_INVALID, "array %u: null pointer", a);
+    if (((uintptr_t)ptrs[a]) % eb != 0) return fail(MS_ERR_INVALID, "array %u: pointer not aligned to %u bytes", a, eb);
+    if (sizes[a] <= 1) continue;
+    if (wave_eligible(hp)) {
+      wave_idx.push_back(a);
+      wave_hp.push_back(hp);
+    } else {
+      large.push_back(a);
+      large_hp.push_back(hp);
+    }
+  }
+  HIP_TRY(hipGetDevice(&g->device));
+  {
+    void* st = nullptr;
+    int rc = graph_alloc(g, 256, &st);
+    if (rc) return rc;
+    g->bufs.pop_back();
+    g->status = reinterpret_cast<uint32_t*>(st);
+    HIP_TRY(hipMemset(g->status, 0, 256));
+  }
+  unsigned long long* spare = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(g->status) + 64);
+  HIP_TRY(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&g->fork, hipEventDisableTiming));
+  for (int i = 0; i < kSideStreams; ++i) {
+    HIP_TRY(hipStreamCreateWithFlags(&g->side[i], hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&g->join[i], hipEventDisableTiming));
+  }
+  // the waves' regions, descriptors written now
+  std::vector<WaveLayout> waves;
+  std::vector<char*> wave_d;
+  const uint32_t wmax = wave_max_arrays();
+  for (size_t i0 = 0; i0 < wave_idx.size();) {
+    WaveLayout w;
+    wave_layout(wave_hp, i0, wave_end(wave_hp, i0, wmax), w);
+    void* d = nullptr;
+    int rc = graph_alloc(g, w.bytes, &d);
+    if (rc) return rc;
+    std::vector<char> h(w.desc_bytes);
+    wave_fill(wave_hp, wave_idx, w, h.data(), reinterpret_cast<char*>(d), ptrs, 0, seeds, d_bits, spare,
+              g->status);
+    HIP_TRY(hipMemcpy(d, h.data(), w.desc_bytes, hipMemcpyHostToDevice));
+    i0 = w.i1;
+    waves.push_back(std::move(w));
+    wave_d.push_back(reinterpret_cast<char*>(d));
+  }
+  // the full-path arrays' plan tables and copies
+  std::vector<void*> ldata(large.size()), lplan(large.size());
+  for (size_t i = 0; i < large.size(); ++i) {
+    const HostPlan& hp = large_hp[i];
+    int rc;
+    if ((rc = graph_alloc(g, hp.nlev ? hp.n * hp.eb : 0, &ldata[i]))) return rc;
+    if ((rc = graph_alloc(g, hp.lay.bytes, &lplan[i]))) return rc;
+  }
+  // capture: full-path arrays on the side streams, waves on the capture stream
+  HIP_TRY(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+  const bool side = !large.empty();
+  int err = MS_OK;
+  if (side) {
+    if (hipEventRecord(g->fork, g->cap) != hipSuccess) err = fail(MS_ERR_HIP, "event record in capture");
+    for (int i = 0; i < kSideStreams && err == MS_OK; ++i)
+      if (hipStreamWaitEvent(g->side[i], g->fork, 0) != hipSuccess) err = fail(MS_ERR_HIP, "stream wait in capture");
+  }
+  for (size_t i = 0; i < large.size() && err == MS_OK; ++i) {
+    const uint32_t a = large[i];
+    err = enqueue_call(large_hp[i], ptrs[a], ldata[i], lplan[i], seeds[a], g->side[i % kSideStreams], nullptr,
+                       nullptr, nullptr, d_bits ? d_bits + a : spare, g->status, false, false);
+  }
+  for (size_t k = 0; k < waves.size() && err == MS_OK; ++k) err = wave_launch(waves[k], wave_d[k], g->cap, false);
+  if (side) {
+    for (int i = 0; i < kSideStreams; ++i) {
+      if (hipEventRecord(g->join[i], g->side[i]) != hipSuccess ||
+          hipStreamWaitEvent(g->cap, g->join[i], 0) != hipSuccess) {
+        if (err == MS_OK) err = fail(MS_ERR_HIP, "join in capture");
       }
     }
-    for (int c = 0; c < kLeafCls; ++c) {
-      if (!nleaf[c]) continue;
-      ProfScope ps(1, st);
-      launch_leaf_multi(reinterpret_cast<const LeafArgs*>(d + leaf_off[c]),
-                        reinterpret_cast<const uint32_t*>(d + wpre_off[c]), nleaf[c], lwg[c],
-                        c / 2 == 0 ? 4u : c / 2 == 1 ? 8u : 16u, (c & 1) != 0, st);
-    }
-    for (auto& kv : gsec) {
-      const uint32_t key = kv.first;
-      const uint32_t lam = key % 4 + 1, cls = (key / 4) % 3;
-      ProfScope ps(2, st);
-      launch_fused_multi(reinterpret_cast<const GroupArgs*>(d + kv.second.off),
-                         reinterpret_cast<const uint32_t*>(d + kv.second.tpre_off), kv.second.n, kv.second.tiles,
-                         (int)lam, cls == 0 ? 4u : cls == 1 ? 8u : 16u, st);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(MS_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
-    i0 = i1;
   }
+  const hipError_t ec = hipStreamEndCapture(g->cap, &g->graph);
+  if (err != MS_OK) return err;
+  if (ec != hipSuccess) return fail(MS_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+  HIP_TRY(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
   return MS_OK;
 }
 
@@ -1033,6 +1250,62 @@ int ms_shuffle_batched(void* const* ptrs, const uint64_t* sizes, uint32_t count,
   return ms_shuffle_batched_ex(ptrs, sizes, nullptr, count, seed, stream, nullptr, nullptr);
 }
 
+int ms_batch_graph_create(void* const* ptrs, const uint64_t* sizes, const uint32_t* elem_bytes,
+                          const uint64_t* seeds, uint32_t count, const ms_config* cfgs,
+                          unsigned long long* d_bits_per_array, ms_batch_graph** out) {
+  g_err.clear();
+  if (!out) return fail(MS_ERR_INVALID, "null output handle");
+  *out = nullptr;
+  if (count && (!ptrs || !sizes || !seeds)) return fail(MS_ERR_INVALID, "null pointer, size or seed array");
+  BatchGraph* g = new BatchGraph;
+  const int rc = graph_build(g, ptrs, sizes, elem_bytes, seeds, count, cfgs, d_bits_per_array);
+  if (rc != MS_OK) {
+    const std::string msg = g_err;
+    graph_free(g);
+    g_err = msg;
+    return rc;
+  }
+  *out = reinterpret_cast<ms_batch_graph*>(g);
+  return MS_OK;
+}
+
+int ms_batch_graph_launch(ms_batch_graph* h, void* stream) {
+  g_err.clear();
+  BatchGraph* g = reinterpret_cast<BatchGraph*>(h);
+  if (!g) return fail(MS_ERR_INVALID, "null graph");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != g->device) return fail(MS_ERR_INVALID, "graph built on device %d, launched on device %d", g->device, dev);
+  HIP_TRY(hipGraphLaunch(g->exec, reinterpret_cast<hipStream_t>(stream)));
+  return MS_OK;
+}
+
+int ms_batch_graph_status(ms_batch_graph* h, void* stream, uint32_t* flags) {
+  g_err.clear();
+  BatchGraph* g = reinterpret_cast<BatchGraph*>(h);
+  if (!g || !flags) return fail(MS_ERR_INVALID, "null graph or output");
+  HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  uint32_t v = 0;
+  HIP_TRY(hipMemcpy(&v, g->status, 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(g->status, 0, 4));
+  *flags = v;
+  return v ? MS_ERR_CAPACITY : MS_OK;
+}
+
+uint64_t ms_batch_graph_bytes(const ms_batch_graph* h) {
+  const BatchGraph* g = reinterpret_cast<const BatchGraph*>(h);
+  return g ? g->bytes : 0;
+}
+
+int ms_batch_graph_destroy(ms_batch_graph* h) {
+  g_err.clear();
+  BatchGraph* g = reinterpret_cast<BatchGraph*>(h);
+  if (!g) return MS_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  graph_free(g);
+  return MS_OK;
+}
+
 int ms_plan(uint64_t n, uint32_t elem_bytes, const ms_config* cfg, ms_plan_info* out) {
   g_err.clear();
   if (!out) return fail(MS_ERR_INVALID, "null output");
@@ -1060,9 +1333,29 @@ uint64_t ms_scratch_bytes(uint64_t n, uint32_t elem_bytes) {
 }
 
 uint32_t ms_leaf_B_for(uint64_t n, uint32_t elem_bytes) {
-  (void)n;
-  (void)elem_bytes;
+  ms_tune_entry e;
+  if (tune_lookup(n, elem_bytes, &e) && e.leaf_B) return e.leaf_B;
   return kDefaultB;
+}
+
+int ms_tune_set(const ms_tune_entry* entries, uint32_t count) {
+  g_err.clear();
+  if (count && !entries) return fail(MS_ERR_INVALID, "null entry array");
+  std::map<uint64_t, ms_tune_entry> t;
+  for (uint32_t i = 0; i < count; ++i) {
+    const ms_tune_entry& e = entries[i];
+    if (e.elem_bytes != 4 && e.elem_bytes != 8 && e.elem_bytes != 16)
+      return fail(MS_ERR_INVALID, "entry %u: element size %u", i, e.elem_bytes);
+    if (e.log2_n > 32) return fail(MS_ERR_INVALID, "entry %u: log2_n %u", i, e.log2_n);
+    if (e.leaf_B == 0 || e.leaf_B + 1 > (uint32_t)leaf_max_block())
+      return fail(MS_ERR_INVALID, "entry %u: cutoff %u", i, e.leaf_B);
+    if (e.levels_per_pass > (uint32_t)kGroupMax) return fail(MS_ERR_INVALID, "entry %u: levels per pass %u", i, e.levels_per_pass);
+    if (e.flags & ~MS_CFG_LEAF_BIG) return fail(MS_ERR_INVALID, "entry %u: flags %u", i, e.flags);
+    t[((uint64_t)e.elem_bytes << 32) | e.log2_n] = e;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.swap(t);
+  return MS_OK;
 }
 
 int ms_device_status(void* stream, uint32_t* flags) {

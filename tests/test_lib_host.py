@@ -126,3 +126,35 @@ def test_listing_placement_plans_every_level_as_one_level_pass():
         assert p1["hbm_levels"] == p1["levels"]
     with pytest.raises(ValueError):
         M.plan(1000, placement="R3")
+
+
+def test_tuning_table_sets_the_cutoff_and_is_validated():
+    M, L = _lib()
+    try:
+        assert M.leaf_B_for(5000) == 4096
+        M.tune_set([{"elem_bytes": 4, "log2_n": 12, "leaf_B": 1000, "levels_per_pass": 2, "leaf_big": True},
+                    {"elem_bytes": 8, "log2_n": 20, "leaf_B": 2048, "levels_per_pass": 0}])
+        assert M.leaf_B_for(4096) == 1000 and M.leaf_B_for(8191) == 1000
+        assert M.leaf_B_for(8192) == 4096 and M.leaf_B_for(4095) == 4096
+        assert M.leaf_B_for(4096, 8) == 4096 and M.leaf_B_for((1 << 20) + 5, 8) == 2048
+        # a tuned call plans with the entry's knobs; an untuned one does not
+        assert M.plan(5000, leaf_B=0)["leaf_B"] == 4096
+        from paper_1508_03167_amd._lib import MS_CFG_TUNED, MSConfig, MSPlanInfo
+
+        info = MSPlanInfo()
+        assert L.ms_plan(5000, 4, ctypes.byref(MSConfig(0, 0, 0, MS_CFG_TUNED)), ctypes.byref(info)) == 0
+        assert info.leaf_B == 1000 and info.levels == 3
+        assert L.ms_plan((1 << 20) + 5, 8, ctypes.byref(MSConfig(0, 0, 0, MS_CFG_TUNED)), ctypes.byref(info)) == 0
+        assert info.leaf_B == 2048
+        # bad entries are refused and the table is kept
+        for bad in ({"elem_bytes": 5, "log2_n": 3, "leaf_B": 10, "levels_per_pass": 0},
+                    {"elem_bytes": 4, "log2_n": 40, "leaf_B": 10, "levels_per_pass": 0},
+                    {"elem_bytes": 4, "log2_n": 3, "leaf_B": 0, "levels_per_pass": 0},
+                    {"elem_bytes": 4, "log2_n": 3, "leaf_B": 5000, "levels_per_pass": 0},
+                    {"elem_bytes": 4, "log2_n": 3, "leaf_B": 10, "levels_per_pass": 5}):
+            with pytest.raises(M.MSError):
+                M.tune_set([bad])
+        assert M.leaf_B_for(5000) == 1000
+    finally:
+        M.tune_set([])
+    assert M.leaf_B_for(5000) == 4096
