@@ -55,18 +55,44 @@ struct MergeAux {
 
 __device__ __forceinline__ uint32_t get16(uint32_t packed, int half) { return (packed >> (16 * half)) & 0xFFFFu; }
 
+// Runs body(i, x, w, ok) for the slots x = lt + tpl * i (i < SPT) of the
+// thread's leaf, without branches: ok tells whether slot x exists (x < b), w
+// is the word of slot x if it does and the spare word `dummy` otherwise, so
+// that a body that addresses its own slot through w and guards everything
+// else by ok runs straight through.  The opaque copy of lt keeps the
+// compiler from computing every slot's address once and holding it across
+// phases.
+template <int SPT, typename Body>
+__device__ __forceinline__ void for_slots(uint32_t lt, uint32_t tpl, uint32_t lb, uint32_t b, uint32_t dummy,
+                                          Body&& body) {
+  uint32_t x0 = lt;
+  asm volatile("" : "+v"(x0));
+#pragma unroll
+  for (int i = 0; i < SPT; ++i) {
+    const uint32_t x = x0 + tpl * (uint32_t)i;
+    const bool ok = x < b;
+    body(i, x, ok ? lb + x : dummy, ok);
+  }
+}
+
+__device__ __forceinline__ uint32_t set16(uint32_t packed, int half, uint32_t v) {
+  return half ? (packed & 0xFFFFu) | (v << 16) : (packed & 0xFFFF0000u) | (v & 0xFFFFu);
+}
+
 // Fisher-Yates of every leaf of the super-block at once (Algorithm 1 per leaf).
 // Before the elements are loaded, the LDS data region holds one 32-bit word
 // per super-block slot: first the slot's draw, then a 16-bit list head
 // (later up()) and the step's 16-bit link (later nxt(), or its draw when no
-// later step targets the same slot).  Each thread owns blocks of 4
-// consecutive steps of one leaf (the steps whose draws share one Philox
-// block) and returns, packed two per register, the leaf-relative source F of
-// each of its slots.
-template <int BPT, int NT>
-__device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uint32_t b, uint32_t u, uint32_t lt,
-                                                uint32_t tpl, Key key, uint32_t* bits, uint32_t* status,
-                                                uint32_t (&F)[BPT][2]) {
+// later step targets the same slot).  For the draws each thread owns blocks
+// of 4 consecutive steps of one leaf (the steps whose draws share one Philox
+// block); for everything else it owns the slots x = lt + tpl * i of its leaf,
+// so that the lanes of a wave touch consecutive LDS words.  It returns,
+// packed two per register, the leaf-relative source F of each of those
+// slots.
+template <int BPT, int SPT, int NT>
+__device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uint32_t b, uint32_t dummy, uint32_t u,
+                                                uint32_t lt, uint32_t tpl, Key key, uint32_t* bits, uint32_t* status,
+                                                uint32_t (&F)[(SPT + 1) / 2]) {
   constexpr uint32_t NONE = 0xFFFFu;
   uint16_t* const half = head;  // the lists' words, as 16-bit halves
 #define HED(y) half[2 * (y)]
@@ -78,37 +104,34 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uin
   //    rounds in total rather than for the slowest lane of every draw.  The
   //    result replaces the word.
   uint32_t* W = reinterpret_cast<uint32_t*>(head);
-#pragma unroll
-  for (int k = 0; k < BPT; ++k) {
-    const uint32_t g = lt + tpl * k;
-    if (4 * g < b) {
-      const W4 db = draw_block(g, u, 0, key);
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (4 * g + e < b) W[lb + 4 * g + e] = db.w[e];
-    }
-  }
   {
-    // The first round of every draw at once (it takes the top bitlen(r)
-    // bits of the word and ends unless they exceed r); the draws it leaves
-    // open then run to the end one after the other per lane.
+    // The first round of every draw as its block comes out of Philox (it
+    // takes the top bitlen(r) bits of the word and ends unless they exceed
+    // r): the word gets the result, or the raw word if the draw stays open;
+    // the open draws then run to the end one after the other per lane.
     constexpr uint32_t QN = 4 * BPT;
     static_assert(QN <= 64, "open draws are tracked in a 64-bit mask");
     uint64_t open = 0;
+    uint32_t nb = 0;
 #pragma unroll
-    for (uint32_t q = 0; q < QN; ++q) {
-      const uint32_t r = 4 * (lt + tpl * (q >> 2)) + (q & 3u);
-      if (r >= 1 && r < b) {
-        const uint32_t bk = 32 - __clz(r);
-        const uint32_t x = W[lb + r] >> (32 - bk);
-        if (x <= r) {
-          W[lb + r] = x;
-          *bits += bk;
-        } else {
-          open |= 1ull << q;
+    for (int k = 0; k < BPT; ++k) {
+      const uint32_t g = lt + tpl * k;
+      if (4 * g < b) {
+        const W4 db = draw_block(g, u, 0, key);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t r = 4 * g + e;
+          const bool ok = r >= 1 && r < b;
+          const uint32_t bk = 32 - __clz(r | 1u);
+          const uint32_t x = db.w[e] >> (32 - bk);
+          const bool first = x <= r;
+          W[ok ? lb + r : dummy] = first ? x : db.w[e];
+          nb += ok && first ? bk : 0u;
+          open |= (uint64_t)(ok && !first) << (4 * k + e);
         }
       }
     }
+    *bits += nb;
     if (open) {
       uint32_t r = 0, w = 0, v = 0, c = 0, used = 0, left = 0, kk = 0, bk = 0;
       auto next = [&]() {
@@ -173,15 +196,16 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uin
   //    first is step y itself).  No list is walked.  Pushes per lane: at most
   //    ceil(ceil(b / ranges) / lanes) <= SCAP / NT + 1 <= 4 * BPT, since a
   //    leaf holds at most SCAP / 2^lds_levels + 1 slots.
-  // (each thread rewrites the words of its own steps: j_r, none for step 0)
-#pragma unroll
-  for (int k = 0; k < BPT; ++k) {
-    const uint32_t g = lt + tpl * k;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint32_t r = 4 * g + e;
-      if (r < b) W[lb + r] = ((r >= 1 ? W[lb + r] : NONE) << 16) | NONE;
-    }
+  // (each thread rewrites the words of its own slots: j_r, none for step 0)
+  // Every loop below runs straight through: a lane whose slot or step does
+  // not exist works on the spare word `dummy` (its two halves as HED/LNK)
+  // and its results are not used.
+  {
+    uint32_t v[SPT];
+    for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t w, bool) { v[i] = W[w]; });
+    for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t r, uint32_t w, bool) {
+      W[w] = ((r >= 1 ? v[i] : NONE) << 16) | NONE;
+    });
   }
   __syncthreads();
   constexpr int ITER = 4 * BPT;  // pushes per lane, at most
@@ -194,17 +218,32 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uin
   uint32_t OLD[(ITER + 1) / 2];  // per pushed step, packed two per register: the head it replaced
   for (uint32_t ph = 0; ph < wpl; ++ph) {
     if (wl == ph) {
+      // in halves of the steps: every target first, then every target's
+      // high half (no push changes a high half), then the exchanges, which
+      // the LDS applies in program order
+      constexpr int H = (ITER + 1) / 2;
 #pragma unroll
-      for (int t = 0; t < ITER; ++t) {
-        const uint32_t r = r0 + lpp * t;
-        uint32_t old = NONE;
-        if (r >= 1 && r < r1) {
-          const uint32_t y = W[lb + r] >> 16;
-          const uint32_t hi = W[lb + y] & 0xFFFF0000u;
-          old = atomicExch(&W[lb + y], hi | r) & 0xFFFFu;
+      for (int h0 = 0; h0 < ITER; h0 += H) {
+        uint32_t wy[H], xv[H];
+#pragma unroll
+        for (int t = 0; t < H; ++t) {
+          const uint32_t r = r0 + lpp * (h0 + t);
+          const bool ok = h0 + t < ITER && r >= 1 && r < r1;
+          const uint32_t y = W[ok ? lb + r : dummy] >> 16;
+          wy[t] = ok ? lb + y : dummy;
         }
-        if (t & 1) OLD[t >> 1] |= old << 16;
-        else OLD[t >> 1] = old;
+#pragma unroll
+        for (int t = 0; t < H; ++t) xv[t] = (W[wy[t]] & 0xFFFF0000u) | (r0 + lpp * (h0 + t));
+#pragma unroll
+        for (int t = 0; t < H; ++t) {
+          if (h0 + t >= ITER) break;
+          const uint32_t r = r0 + lpp * (h0 + t);
+          const bool ok = r >= 1 && r < r1;
+          const uint32_t x = atomicExch(&W[wy[t]], xv[t]) & 0xFFFFu;
+          const uint32_t old = ok ? x : NONE;
+          if ((h0 + t) & 1) OLD[(h0 + t) >> 1] |= old << 16;
+          else OLD[(h0 + t) >> 1] = old;
+        }
       }
     }
     __syncthreads();
@@ -215,30 +254,50 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uin
   // j_r; j_r = r marks a self push); the step pushed next onto the same slot
   // then makes itself the link.
   constexpr uint32_t NOLATER = 0x8000u;
+  {
+    // (every target is read before the first write; the writes touch the
+    // heads of targets and the links of this lane's own steps)
+    uint32_t y[ITER];
 #pragma unroll
-  for (int t = 0; t < ITER; ++t) {
-    const uint32_t r = r0 + lpp * t;
-    if (r >= 1 && r < r1) {
+    for (int t = 0; t < ITER; ++t) {
+      const uint32_t r = r0 + lpp * t;
+      y[t] = W[r >= 1 && r < r1 ? lb + r : dummy] >> 16;
+    }
+#pragma unroll
+    for (int t = 0; t < ITER; ++t) {
+      const uint32_t r = r0 + lpp * t;
+      const bool ok = r >= 1 && r < r1;
       const uint32_t old = get16(OLD[t >> 1], t & 1);
-      const uint32_t y = W[lb + r] >> 16;
-      if (old == NONE) HED(lb + y) = (uint16_t)(r != y ? r : NONE);
-      LNK(lb + r) = (uint16_t)(y | NOLATER);
+      HED(ok && old == NONE ? lb + y[t] : dummy) = (uint16_t)(r != y[t] ? r : NONE);
+      LNK(ok ? lb + r : dummy) = (uint16_t)(y[t] | NOLATER);
     }
   }
   __syncthreads();
+  {
+    // Each old step is the predecessor of exactly one pushed step, so its
+    // word is this lane's alone here: all of them are read, then written.
+    // Pushes onto one slot came in increasing step order; a lane that sees
+    // otherwise reports it (bit 3), the lists are then unordered.
+    bool unordered = false;
+    uint32_t wv[ITER];
 #pragma unroll
-  for (int t = 0; t < ITER; ++t) {
-    const uint32_t r = r0 + lpp * t;
-    if (r >= 1 && r < r1) {
+    for (int t = 0; t < ITER; ++t) {
+      const uint32_t r = r0 + lpp * t;
       const uint32_t old = get16(OLD[t >> 1], t & 1);
-      if (old != NONE) {
-        // pushes onto one slot came in increasing step order; a lane that
-        // sees otherwise reports it (bit 3), the lists are then unordered
-        if (old > r) atomicOr(status, 8u);
-        if (LNK(lb + old) == (old | NOLATER)) HED(lb + old) = (uint16_t)r;
-        LNK(lb + old) = (uint16_t)r;
-      }
+      const bool ok = r >= 1 && r < r1 && old != NONE;
+      wv[t] = W[ok ? lb + old : dummy];
     }
+#pragma unroll
+    for (int t = 0; t < ITER; ++t) {
+      const uint32_t r = r0 + lpp * t;
+      const uint32_t old = get16(OLD[t >> 1], t & 1);
+      const bool ok = r >= 1 && r < r1 && old != NONE;
+      unordered |= ok && old > r;
+      const uint32_t lk = wv[t] >> 16, hd = wv[t] & 0xFFFFu;
+      // head (low half) and link (high half) of the old step's word
+      W[ok ? lb + old : dummy] = (r << 16) | (lk == (old | NOLATER) ? r : hd);
+    }
+    if (unordered) atomicOr(status, 8u);
   }
   __syncthreads();
   // 4. top() of every slot by pointer jumping over the up() links (each
@@ -248,44 +307,36 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uin
   //    half and writes the other, one barrier per round.  A slot whose
   //    pointer is NONE or points at a chain end is final; it writes its value
   //    to both halves and drops out of the later rounds.
-  static_assert(4 * BPT <= 64, "live slots are tracked in a 64-bit mask");
+  static_assert(SPT <= 64, "live slots are tracked in a 64-bit mask");
 #pragma unroll
-  for (int k = 0; k < BPT; ++k) {
-    const uint32_t g = lt + tpl * k;
-    uint32_t lk[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint32_t x = 4 * g + e;
-      lk[e] = x >= 1 && x < b ? (uint32_t)LNK(lb + x) : 0u;
-    }
-    F[k][0] = lk[0] | (lk[1] << 16);
-    F[k][1] = lk[2] | (lk[3] << 16);
-  }
+  for (int i = 0; i < (SPT + 1) / 2; ++i) F[i] = 0u;
+  for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t x, uint32_t w, bool) {
+    const uint32_t l = LNK(w);
+    F[i >> 1] = set16(F[i >> 1], i & 1, x >= 1 ? l : 0u);
+  });
   __syncthreads();
   uint64_t live = 0;
-#pragma unroll
-  for (int k = 0; k < BPT; ++k) {
-    const uint32_t g = lt + tpl * k;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint32_t x = 4 * g + e;
-      if (x < b) {
-        const uint32_t t = HED(lb + x);
-        const uint32_t tt = t != NONE ? (uint32_t)HED(lb + t) : NONE;
-        LNK(lb + x) = (uint16_t)(tt != NONE ? tt : t);
-        if (tt != NONE) live |= 1ull << (4 * k + e);
-      }
-    }
+  {
+    uint32_t t[SPT], tt[SPT];
+    for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t w, bool) { t[i] = HED(w); });
+    for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t, bool ok) {
+      tt[i] = HED(ok && t[i] != NONE ? lb + t[i] : dummy);
+    });
+    for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t w, bool ok) {
+      const bool two = ok && t[i] != NONE && tt[i] != NONE;
+      LNK(w) = (uint16_t)(two ? tt[i] : t[i]);
+      live |= (uint64_t)two << i;
+    });
   }
   bool rd_high = true;  // this round reads the high halves
   while (__syncthreads_or(live != 0)) {
     uint64_t m = live, nl = 0;
+    uint16_t* rd = rd_high ? &LNK(0) : &HED(0);
+    uint16_t* wr = rd_high ? &HED(0) : &LNK(0);
     while (m) {
       const int q = __builtin_ctzll(m);
       m &= m - 1;
-      const uint32_t x = lb + 4 * (lt + tpl * (uint32_t)(q >> 2)) + (uint32_t)(q & 3);
-      uint16_t* rd = rd_high ? &LNK(0) : &HED(0);
-      uint16_t* wr = rd_high ? &HED(0) : &LNK(0);
+      const uint32_t x = lb + lt + tpl * (uint32_t)q;
       const uint32_t t = rd[2 * x];
       const uint32_t tt = rd[2 * (lb + t)];
       if (tt == NONE) {
@@ -299,30 +350,16 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uin
     live = nl;
     rd_high = !rd_high;
   }
-  // both halves of x's word now hold the end of x's up() chain, or NONE if x has no up()
-#pragma unroll
-  for (int k = 0; k < BPT; ++k) {
-    const uint32_t g = lt + tpl * k;
-    uint32_t f[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint32_t x = 4 * g + e;
-      // step x's link: a later step on its slot, or its own target with
-      // bit 15 set; slot 0 starts from itself
-      const uint32_t lk = get16(F[k][e >> 1], e & 1);
-      f[e] = 0u;
-      if (x < b) {
-        if (lk & NOLATER) {
-          f[e] = lk & ~NOLATER;
-        } else {
-          const uint32_t top = HED(lb + lk);
-          f[e] = top != NONE ? top : lk;
-        }
-      }
-    }
-    F[k][0] = (f[0] & 0xFFFFu) | (f[1] << 16);
-    F[k][1] = (f[2] & 0xFFFFu) | (f[3] << 16);
-  }
+  // both halves of x's word now hold the end of x's up() chain, or NONE if x
+  // has no up().  Step x's link: a later step on its slot, or its own target
+  // with bit 15 set; slot 0 starts from itself.  A slot that does not exist
+  // gets source 0.
+  for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t, bool ok) {
+    const uint32_t lk = get16(F[i >> 1], i & 1);
+    const uint32_t top = HED(lb + (lk & ~NOLATER));
+    uint32_t f = (lk & NOLATER) ? lk & ~NOLATER : (top != NONE ? top : lk);
+    F[i >> 1] = set16(F[i >> 1], i & 1, ok ? f : 0u);
+  });
   __syncthreads();
 #undef HED
 #undef LNK
@@ -417,13 +454,78 @@ __device__ __forceinline__ void lds_merge_tail(E* data, uint32_t* seen, uint32_t
 
 // One super-block sb of 2^lds_levels leaves: Fisher-Yates of each leaf, then
 // the merge levels among them, all in LDS.
+// Copy cnt elements between global memory and LDS (LDS side 16-byte
+// aligned): the whole 16-byte groups of the global side move as 16-byte
+// accesses, every load of a thread issued before its first store; the
+// ragged ends move element by element.  MAXV bounds the groups per thread.
+template <typename E, int NT, int MAXV, bool TO_LDS>
+__device__ __forceinline__ void copy_block(E* lds, E* glob, uint32_t cnt) {
+  constexpr uint32_t PER = 16 / sizeof(E);
+  const uint32_t mis = (uint32_t)((uintptr_t)glob & 15u);
+  const uint32_t h = min(cnt, (uint32_t)(((16u - mis) & 15u) / sizeof(E)));
+  const uint32_t groups = (cnt - h) / PER;
+  const uint32_t tail0 = h + groups * PER;
+  const uint32_t tid = threadIdx.x;
+  if (tid < h) {
+    if (TO_LDS) lds[tid] = glob[tid];
+    else glob[tid] = lds[tid];
+  }
+  if (tid < cnt - tail0) {
+    if (TO_LDS) lds[tail0 + tid] = glob[tail0 + tid];
+    else glob[tail0 + tid] = lds[tail0 + tid];
+  }
+  uint4* g4 = reinterpret_cast<uint4*>(glob + h);
+  uint4 v[MAXV];
+  if (TO_LDS) {
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+      const uint32_t q = tid + NT * k;
+      if (q < groups) v[k] = g4[q];
+    }
+  }
+  if (h == 0) {
+    uint4* l4 = reinterpret_cast<uint4*>(lds);
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+      const uint32_t q = tid + NT * k;
+      if (q < groups) {
+        if (TO_LDS) l4[q] = v[k];
+        else v[k] = l4[q];
+      }
+    }
+  } else {
+    // the LDS side is off the 16-byte grid: element accesses
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+      const uint32_t q = tid + NT * k;
+      if (q < groups) {
+        E* e = reinterpret_cast<E*>(&v[k]);
+#pragma unroll
+        for (uint32_t c = 0; c < PER; ++c) {
+          if (TO_LDS) lds[h + q * PER + c] = e[c];
+          else e[c] = lds[h + q * PER + c];
+        }
+      }
+    }
+  }
+  if (!TO_LDS) {
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+      const uint32_t q = tid + NT * k;
+      if (q < groups) g4[q] = v[k];
+    }
+  }
+}
+
 template <typename E, int SCAP, int NT, bool IDENT>
 __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) {
   constexpr int KW = (MergeAux<SCAP>::kWords + NT - 1) / NT;  // words per thread in scans
   constexpr int KS = (SCAP + NT - 1) / NT;                     // slots per thread
   constexpr int BPT = (SCAP / 4 + kLeafMaxMerges + NT - 1) / NT;  // step blocks per thread
+  constexpr int SPT = SCAP / NT + 1;                              // slots of a leaf per thread, at most
+  constexpr int MAXV = (int)((SCAP * sizeof(E) / 16 + NT - 1) / NT);  // 16-byte groups per thread
   static_assert(SCAP * sizeof(E) >= 4 * SCAP, "list heads and links live in the data region");
-  __shared__ __align__(16) E data[SCAP];
+  __shared__ __align__(16) E data[SCAP + 1];  // one spare element: the word straight loops write to
   __shared__ MergeAux<SCAP> maux;
   __shared__ uint32_t tmp[20];
   __shared__ uint32_t mP[kLeafMaxMerges];
@@ -448,40 +550,28 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
   const uint32_t lb = (uint32_t)(bound(a.n, u, a.c) - base);
   const uint32_t b = (uint32_t)(bound(a.n, u + 1, a.c) - bound(a.n, u, a.c));
   uint16_t* head = reinterpret_cast<uint16_t*>(data);
-  uint32_t F[BPT][2];
-  // touch one word of every 128-byte line of the super-block's input now, so
-  // that the load after the Fisher-Yates phase finds it in L2
-  uint32_t touch = 0;
-  if (!IDENT) {
-    const uint32_t per_line = 128 / sizeof(E);
-    const uint32_t line = (uint32_t)tid * per_line;
-    if (line < cnt) touch = *reinterpret_cast<const uint32_t*>(in + base + line);
-  }
-  leaf_fy_sources<BPT, NT>(head, lb, b, (uint32_t)u, lt, tpl, key, &bits, a.status, F);
-  asm volatile("" ::"v"(touch));
+  uint32_t F[(SPT + 1) / 2];
+  // the spare word past the super-block's slots (lists use one word per slot)
+  constexpr uint32_t kDummy = SCAP * sizeof(E) / 4;
+  leaf_fy_sources<BPT, SPT, NT>(head, lb, b, kDummy, (uint32_t)u, lt, tpl, key, &bits, a.status, F);
   (void)nleaf;
 
-  for (uint32_t i = tid; i < cnt; i += NT) data[i] = IDENT ? ident_value<E>(base + i) : in[base + i];
+  if (IDENT) {
+    for (uint32_t i = tid; i < cnt; i += NT) data[i] = ident_value<E>(base + i);
+  } else {
+    copy_block<E, NT, MAXV, true>(data, const_cast<E*>(in) + base, cnt);
+  }
   __syncthreads();
   {
     using R = typename RegOf<E>::type;
     R* dataR = reinterpret_cast<R*>(data);
-    R val[BPT][4];
-#pragma unroll
-    for (int k = 0; k < BPT; ++k) {
-      const uint32_t g = lt + tpl * k;
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (4 * g + e < b) val[k][e] = dataR[lb + get16(F[k][e >> 1], e & 1)];
-    }
+    R val[SPT];
+    // (a slot that does not exist has source 0 and writes the spare element)
+    for_slots<SPT>(lt, tpl, lb, b, SCAP, [&](int i, uint32_t, uint32_t, bool) {
+      val[i] = dataR[lb + get16(F[i >> 1], i & 1)];
+    });
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < BPT; ++k) {
-      const uint32_t g = lt + tpl * k;
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (4 * g + e < b) dataR[lb + 4 * g + e] = val[k][e];
-    }
+    for_slots<SPT>(lt, tpl, lb, b, SCAP, [&](int i, uint32_t, uint32_t w, bool) { dataR[w] = val[i]; });
     __syncthreads();
   }
 
@@ -651,7 +741,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
     __syncthreads();
   }
 
-  for (uint32_t i = tid; i < cnt; i += NT) out[base + i] = data[i];
+  copy_block<E, NT, MAXV, false>(data, out + base, cnt);
   const uint64_t t = block_sum_u64<NT>(bits, red);
   if (tid == 0 && t) atomicAdd(a.bits, (unsigned long long)t);
 }
