@@ -300,13 +300,14 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uin
     if (unordered) atomicOr(status, 8u);
   }
   __syncthreads();
-  // 4. top() of every slot by pointer jumping over the up() links (each
-  //    round halves the remaining chains), then F[r] = top(nxt(r)) or j_r,
-  //    F[0] = top(0).  F first takes each slot's link (nxt(x), or j_x with
-  //    bit 15 set), which frees the high halves: the jumping then reads one
-  //    half and writes the other, one barrier per round.  A slot whose
-  //    pointer is NONE or points at a chain end is final; it writes its value
-  //    to both halves and drops out of the later rounds.
+  // 4. top() of every slot: the end of its chain of up() links (NONE if it
+  //    has no up()), then F[r] = top(nxt(r)) or j_r, F[0] = top(0).  F
+  //    first takes each slot's link (nxt(x), or j_x with bit 15 set), which
+  //    frees the link halves; the head halves keep the up() links, which
+  //    nothing changes from here on, so every lane follows the chains of its
+  //    own slots with no barrier: two steps for every slot at once (most
+  //    chains are that short), then the rest one slot at a time, writing
+  //    top() to the slot's link half.
   static_assert(SPT <= 64, "live slots are tracked in a 64-bit mask");
 #pragma unroll
   for (int i = 0; i < (SPT + 1) / 2; ++i) F[i] = 0u;
@@ -315,48 +316,41 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uin
     F[i >> 1] = set16(F[i >> 1], i & 1, x >= 1 ? l : 0u);
   });
   __syncthreads();
-  uint64_t live = 0;
   {
-    uint32_t t[SPT], tt[SPT];
-    for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t w, bool) { t[i] = HED(w); });
-    for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t, bool ok) {
-      tt[i] = HED(ok && t[i] != NONE ? lb + t[i] : dummy);
-    });
-    for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t w, bool ok) {
-      const bool two = ok && t[i] != NONE && tt[i] != NONE;
-      LNK(w) = (uint16_t)(two ? tt[i] : t[i]);
-      live |= (uint64_t)two << i;
-    });
-  }
-  bool rd_high = true;  // this round reads the high halves
-  while (__syncthreads_or(live != 0)) {
-    uint64_t m = live, nl = 0;
-    uint16_t* rd = rd_high ? &LNK(0) : &HED(0);
-    uint16_t* wr = rd_high ? &HED(0) : &LNK(0);
-    while (m) {
-      const int q = __builtin_ctzll(m);
-      m &= m - 1;
-      const uint32_t x = lb + lt + tpl * (uint32_t)q;
-      const uint32_t t = rd[2 * x];
-      const uint32_t tt = rd[2 * (lb + t)];
-      if (tt == NONE) {
-        wr[2 * x] = (uint16_t)t;
-        rd[2 * x] = (uint16_t)t;
-      } else {
-        wr[2 * x] = (uint16_t)tt;
-        nl |= 1ull << q;
-      }
+    uint64_t live = 0;
+    {
+      uint32_t t[SPT], tt[SPT];
+      for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t w, bool) { t[i] = HED(w); });
+      for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t, bool ok) {
+        tt[i] = HED(ok && t[i] != NONE ? lb + t[i] : dummy);
+      });
+      for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t w, bool ok) {
+        const bool two = ok && t[i] != NONE && tt[i] != NONE;
+        LNK(w) = (uint16_t)(two ? tt[i] : t[i]);
+        live |= (uint64_t)two << i;
+      });
     }
-    live = nl;
-    rd_high = !rd_high;
+    while (live) {
+      const int q = __builtin_ctzll(live);
+      live &= live - 1;
+      const uint32_t x = lb + lt + tpl * (uint32_t)q;
+      uint32_t cur = LNK(x);
+      for (;;) {
+        const uint32_t nx = HED(lb + cur);
+        if (nx == NONE) break;
+        cur = nx;
+      }
+      LNK(x) = (uint16_t)cur;
+    }
   }
-  // both halves of x's word now hold the end of x's up() chain, or NONE if x
-  // has no up().  Step x's link: a later step on its slot, or its own target
-  // with bit 15 set; slot 0 starts from itself.  A slot that does not exist
-  // gets source 0.
+  __syncthreads();
+  // the link half of x's word now holds the end of x's up() chain, or NONE
+  // if x has no up().  Step x's link: a later step on its slot, or its own
+  // target with bit 15 set; slot 0 starts from itself.  A slot that does not
+  // exist gets source 0.
   for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t, bool ok) {
     const uint32_t lk = get16(F[i >> 1], i & 1);
-    const uint32_t top = HED(lb + (lk & ~NOLATER));
+    const uint32_t top = LNK(lb + (lk & ~NOLATER));
     uint32_t f = (lk & NOLATER) ? lk & ~NOLATER : (top != NONE ? top : lk);
     F[i >> 1] = set16(F[i >> 1], i & 1, ok ? f : 0u);
   });
