@@ -58,6 +58,38 @@ def test_permutation_n2p30_seed7(M):
     torch.cuda.empty_cache()
 
 
+def test_permutation_largest_accepted_size(M):
+    # n = 2^32 - 2^16, the largest n the library accepts: slot indices use all
+    # 32 bits, the top merge spans the whole array
+    import torch
+
+    g = _golden("perm_n2^32-2^16_seed5")
+    n = g["n"]
+    print(f"[gpu] largest-size permutation n={n} seed={g['seed']}", flush=True)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    bits = torch.zeros(1, dtype=torch.int64, device="cuda")
+    M.permutation(out, g["seed"], bits=bits)
+    torch.cuda.synchronize()
+    assert M.device_status() == 0
+    assert int(bits.item()) == g["bits"]
+    pos = torch.tensor([p for p, _ in g["samples"]], dtype=torch.int64, device="cuda")
+    got = (out[pos].to(torch.int64) & 0xFFFFFFFF).cpu().numpy()
+    assert got.tolist() == [v for _, v in g["samples"]]
+    assert list(hashing.fingerprint_torch(out)) == g["fingerprint"]
+    # a permutation of 0..n-1: the sums of the values and of their squares
+    # (modulo 2^64) are those of the identity
+    s1 = s2 = 0
+    for a in range(0, n, 1 << 26):
+        v = out[a:a + (1 << 26)].to(torch.int64) & 0xFFFFFFFF
+        s1 += int(v.sum().item())
+        s2 = (s2 + int((v * v).sum().item())) % (1 << 64)
+    assert s1 == n * (n - 1) // 2
+    assert s2 == ((n - 1) * n * (2 * n - 1) // 6) % (1 << 64)
+    del out
+    M.release()
+    torch.cuda.empty_cache()
+
+
 def test_records16_n2p27_seed11(M):
     import torch
 
