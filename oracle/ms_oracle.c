@@ -338,7 +338,7 @@ uint32_t oracle_levels(uint64_t n, uint64_t cutoff) { return levels_for(n, cutof
 static uint64_t bound(uint64_t n, uint64_t i, uint32_t c) { return (n * i) >> c; }
 
 static uint64_t run_shuffle(osrc *proto, uint32_t *t, uint64_t n, uint64_t cutoff,
-                            int placement, uint64_t *P_out, int threads)
+                            int placement, int threads)
 {
     uint32_t c, L;
     uint64_t q, i, bits = 0;
@@ -381,17 +381,14 @@ static uint64_t run_shuffle(osrc *proto, uint32_t *t, uint64_t n, uint64_t cutof
             osrc s = *proto;
             uint64_t i0 = m * 2 * p;
             uint64_t j = bound(n, i0, c), k = bound(n, i0 + p, c), l = bound(n, i0 + 2 * p, c);
-            uint64_t P;
             osrc *sp = proto->script ? proto : &s;
             s.bits = 0; s.memo_ok = 0;
             if (placement == ORACLE_R2)
-                P = merge_r2(sp, t + j, k - j, l - k, L, (uint32_t)m, tmp + j);
+                merge_r2(sp, t + j, k - j, l - k, L, (uint32_t)m, tmp + j);
             else if (placement == ORACLE_BALANCED)
-                P = merge_balanced(sp, t + j, k - j, l - k, L, (uint32_t)m, tmp + j, word + j);
+                merge_balanced(sp, t + j, k - j, l - k, L, (uint32_t)m, tmp + j, word + j);
             else
-                P = merge_r1(sp, t + j, k - j, l - k, L, (uint32_t)m);
-            /* merges of level L are stored after those of levels 1..L-1 */
-            if (P_out) P_out[q - (q >> (L - 1)) + m] = P;
+                merge_r1(sp, t + j, k - j, l - k, L, (uint32_t)m);
             bits += s.bits;
         }
     }
@@ -407,18 +404,7 @@ uint64_t oracle_shuffle_u32(uint32_t *t, uint64_t n, uint64_t cutoff, uint64_t s
     osrc s;
     memset(&s, 0, sizeof s);
     s.seed = seed;
-    return run_shuffle(&s, t, n, cutoff, placement, NULL, threads);
-}
-
-/* As oracle_shuffle_u32, also writing P of every merge: level L's merge m
- * at index q - q/2^(L-1) + m (q - 1 entries in all, q = 2^levels). */
-uint64_t oracle_shuffle_trace(uint32_t *t, uint64_t n, uint64_t cutoff, uint64_t seed,
-                              int placement, uint64_t *P_out, int threads)
-{
-    osrc s;
-    memset(&s, 0, sizeof s);
-    s.seed = seed;
-    return run_shuffle(&s, t, n, cutoff, placement, P_out, threads);
+    return run_shuffle(&s, t, n, cutoff, placement, threads);
 }
 
 /* out[i] = i, then shuffle: the random permutation of size n. */
@@ -444,7 +430,7 @@ int oracle_shuffle_scripted(uint32_t *t, uint64_t n, uint64_t cutoff, int placem
     memset(&s, 0, sizeof s);
     s.script = script;
     s.script_len = script_len;
-    run_shuffle(&s, t, n, cutoff, placement, NULL, 1);
+    run_shuffle(&s, t, n, cutoff, placement, 1);
     if (consumed) *consumed = s.script_pos;
     if (need) *need = s.starved ? s.need : 0;
     return s.starved;

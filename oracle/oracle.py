@@ -51,9 +51,6 @@ def lib():
         L.oracle_shuffle_u32.argtypes = [u32p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                          ctypes.c_int, ctypes.c_int]
         L.oracle_shuffle_u32.restype = ctypes.c_uint64
-        L.oracle_shuffle_trace.argtypes = [u32p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
-                                           ctypes.c_int, u64p, ctypes.c_int]
-        L.oracle_shuffle_trace.restype = ctypes.c_uint64
         L.oracle_permutation.argtypes = [u32p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                          ctypes.c_int]
         L.oracle_permutation.restype = ctypes.c_uint64
@@ -112,17 +109,6 @@ def permutation(n: int, cutoff: int, seed: int, threads: int = 1):
     out = np.empty(n, dtype=np.uint32)
     bits = int(lib().oracle_permutation(_u32(out), n, cutoff, seed & (2**64 - 1), threads))
     return out, bits
-
-
-def shuffle_trace(n: int, cutoff: int, seed: int, placement: int = R2, threads: int = 1):
-    """(pi, bits, P) with P[q - q/2^(L-1) + m] = coin-flip prefix of merge (L, m)."""
-    c = levels(n, cutoff)
-    q = 1 << c
-    out = np.arange(n, dtype=np.uint32)
-    P = np.zeros(max(q - 1, 1), dtype=np.uint64)
-    bits = int(lib().oracle_shuffle_trace(_u32(out), n, cutoff, seed & (2**64 - 1), placement,
-                                          P.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), threads))
-    return out, bits, P[: q - 1]
 
 
 def shuffle_scripted(n: int, cutoff: int, script, placement: int = R2):
