@@ -181,6 +181,32 @@ def bench_r1(M, torch, n_log2: int = 26, seed: int = 7, reps: int = 5):
             "stable_one_level_hbm_only_ms": round(t2 * 1e3, 3), "default_path_ms": round(t0 * 1e3, 3)}
 
 
+def bench_balanced(M, torch, n_log2: int = 26, seed: int = 7, reps: int = 5):
+    """BalancedShuffle (Section 2): every level a one-level HBM pass over the
+    final side labels the plan writes, against the default merge run the
+    same way (one-level passes, every level in HBM) and the default path."""
+    n = 1 << n_log2
+    x = torch.empty(n, dtype=torch.int32, device="cuda:0")
+
+    def timed(**kw):
+        M.permutation(x, seed, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            M.permutation(x, seed, **kw)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    tb = timed(placement="BAL")
+    t2 = timed(hbm_only=True, one_level_passes=True)
+    t0 = timed()
+    del x
+    return {"workload": f"MergeShuffle permutation of 0..2^{n_log2}-1, seed {seed}, cutoff 4096, "
+                        f"BalancedShuffle merges",
+            "n": n, "balanced_ms": round(tb * 1e3, 3), "balanced_gelem_s": round(n / tb / 1e9, 3),
+            "stable_one_level_hbm_only_ms": round(t2 * 1e3, 3), "default_path_ms": round(t0 * 1e3, 3)}
+
+
 def _timed_classes(M, torch, fn, reps: int):
     """Wall time per call of fn() and the library's per-class kernel times."""
     fn()
@@ -296,7 +322,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=29)
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the batched, served, listing-placement, records and small workloads")
+                    help="skip the batched, served, listing-placement, balanced, records and small workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 2^28 uint32 (1 GiB) for counter calibration")
     args = ap.parse_args()
@@ -397,6 +423,8 @@ def main():
         out["served"] = bench_served(M, torch)
         torch.cuda.empty_cache()
         out["r1_placement"] = bench_r1(M, torch)
+        torch.cuda.empty_cache()
+        out["balanced"] = bench_balanced(M, torch)
         torch.cuda.empty_cache()
         out["records"] = bench_records(M, torch)
         torch.cuda.empty_cache()

@@ -110,6 +110,17 @@ typedef struct ms_config {
  * one (see ms_tune_set); the other fields as given.  The tuned cutoff changes
  * the permutation like any cutoff: ms_leaf_B_for reports it. */
 #define MS_CFG_TUNED 16u
+/* MS_CFG_PLACEMENT_BALANCED: BalancedShuffle (Section 2): every merge
+ * interleaves its two shuffled halves by a uniformly random word of
+ * C(n1+n2, n1) -- the side labels that Algorithm 2 leaves when it merges the
+ * labels 0^n1 1^n2 (its coin flips up to the break step, the remaining side
+ * after it, then its insertion loop applied to the labels), drawn with the
+ * same bits, break steps and draws as the default merge -- and slot k takes
+ * the next element of the side its label names.  Every merge level runs as a
+ * one-level HBM pass (implies MS_CFG_HBM_ONLY and MS_CFG_ONE_LEVEL_PASSES);
+ * the plan materializes each level's final labels (one bit per element).
+ * Not combinable with MS_CFG_PLACEMENT_R1. */
+#define MS_CFG_PLACEMENT_BALANCED 32u
 
 /* Shuffle n elements of elem_bytes bytes at dev_ptr in place (Algorithm
  * MergeShuffle with cutoff 4096), seed as above, on stream. */

@@ -23,6 +23,7 @@ MS_CFG_ONE_LEVEL_PASSES = 2
 MS_CFG_PLACEMENT_R1 = 4
 MS_CFG_LEAF_BIG = 8
 MS_CFG_TUNED = 16
+MS_CFG_PLACEMENT_BALANCED = 32
 
 SYMBOLS = [
     "ms_shuffle", "ms_permutation", "ms_shuffle_batched", "ms_shuffle_ex", "ms_permutation_ex",
@@ -115,14 +116,16 @@ def _check(rc: int):
 
 def _cfg(leaf_B=0, lds_levels_max=0, hbm_only=False, levels_per_pass=0, one_level_passes=False, placement="R2",
          leaf_big=False, tuned=False):
-    if placement not in ("R1", "R2"):
-        raise ValueError(f"placement {placement!r} is neither 'R1' nor 'R2'")
+    if placement not in ("R1", "R2", "BAL"):
+        raise ValueError(f"placement {placement!r} is none of 'R1', 'R2', 'BAL'")
     r1 = placement == "R1"
-    if not (leaf_B or lds_levels_max or hbm_only or levels_per_pass or one_level_passes or r1 or leaf_big or tuned):
+    bal = placement == "BAL"
+    if not (leaf_B or lds_levels_max or hbm_only or levels_per_pass or one_level_passes or r1 or bal or leaf_big
+            or tuned):
         return None
     flags = ((MS_CFG_HBM_ONLY if hbm_only else 0) | (MS_CFG_ONE_LEVEL_PASSES if one_level_passes else 0)
-             | (MS_CFG_PLACEMENT_R1 if r1 else 0) | (MS_CFG_LEAF_BIG if leaf_big else 0)
-             | (MS_CFG_TUNED if tuned else 0))
+             | (MS_CFG_PLACEMENT_R1 if r1 else 0) | (MS_CFG_PLACEMENT_BALANCED if bal else 0)
+             | (MS_CFG_LEAF_BIG if leaf_big else 0) | (MS_CFG_TUNED if tuned else 0))
     return ctypes.byref(MSConfig(leaf_B, levels_per_pass, lds_levels_max, flags))
 
 
@@ -144,7 +147,8 @@ def shuffle_(t, seed: int, *, stream=None, bits=None, leaf_B=0, lds_levels_max=0
              levels_per_pass=0, one_level_passes=False, placement="R2", leaf_big=False, tuned=False):
     """Shuffle the contiguous device tensor t in place along its first dimension
     (row size 4, 8 or 16 bytes).  bits: optional int64 device tensor, += bits used.
-    placement "R1" places each merge's elements as the printed listing's swaps do."""
+    placement "R1" places each merge's elements as the printed listing's swaps do;
+    "BAL" merges by BalancedShuffle's uniform word (Section 2)."""
     assert t.is_cuda and t.is_contiguous()
     eb = t.element_size() * (t[0].numel() if t.dim() > 1 else 1)
     n = t.shape[0]

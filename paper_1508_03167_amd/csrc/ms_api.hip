@@ -102,7 +102,7 @@ constexpr uint32_t kDefaultB = 4096;
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t zloc, ctot, zc, zg, P, side, kcnt, toff, tail_src, bcnt, bfill, boff, part, pool_x, pool_step, pool_src,
-      tail_xsrc, pool_xsrc, bnd, desc, bits_part;
+      tail_xsrc, pool_xsrc, bnd, desc, bits_part, lab;
   size_t bytes;
 };
 
@@ -182,8 +182,10 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
   uint32_t lam_max = (uint32_t)leaf_max_levels();
   if (cfg && cfg->lds_levels_max && cfg->lds_levels_max < lam_max) lam_max = cfg->lds_levels_max;
   const bool r1 = cfg && (cfg->flags & MS_CFG_PLACEMENT_R1);
+  const bool bal = cfg && (cfg->flags & MS_CFG_PLACEMENT_BALANCED);
+  if (r1 && bal) return fail(MS_ERR_INVALID, "MS_CFG_PLACEMENT_R1 and MS_CFG_PLACEMENT_BALANCED together");
   if (cfg && (cfg->flags & MS_CFG_HBM_ONLY)) lam_max = 0;  // every merge level as an HBM pass
-  if (r1) lam_max = 0;  // the leaf kernel's merge levels use the stable interleave
+  if (r1 || bal) lam_max = 0;  // the leaf kernel's merge levels use the stable interleave
   uint32_t lam = 0;
   while (lam < c && lam < lam_max && ceil_shift(n, c - lam - 1) <= scap) ++lam;
   hp.lam = lam;
@@ -239,8 +241,8 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
   if (cfg && cfg->levels_per_pass) lpp = cfg->levels_per_pass;
   else if (hp.nlev >= 13 && (eb != 4 || hp.nlev % 3 != 0)) lpp = 4u;
   if (lpp > (uint32_t)kGroupMax) lpp = kGroupMax;
-  hp.fused = !(cfg && (cfg->flags & MS_CFG_ONE_LEVEL_PASSES)) && !r1;
-  pa.placement = r1 ? 1u : 0u;
+  hp.fused = !(cfg && (cfg->flags & MS_CFG_ONE_LEVEL_PASSES)) && !r1 && !bal;
+  pa.placement = r1 ? 1u : bal ? 2u : 0u;
   if (!hp.fused) lpp = 1;
   hp.ngroup = hp.nlev ? (hp.nlev + lpp - 1) / lpp : 0;
   {
@@ -318,6 +320,7 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
   y.bnd = hp.fused ? take(all_bnd * kBndStride * 4) : 0;
   y.desc = hp.fused ? take(all_desc * 4) : 0;
   y.bits_part = take(kBitsParts * 8);
+  y.lab = bal ? take(chunks * 1024 * 4) : 0;
   y.bytes = hp.nlev ? o : 0;
   return MS_OK;
 }
@@ -477,6 +480,7 @@ void bind_plan(HostPlan& hp, void* area) {
   pa.bnd = hp.fused ? reinterpret_cast<uint32_t*>(b + y.bnd) : nullptr;
   pa.desc = hp.fused ? reinterpret_cast<uint32_t*>(b + y.desc) : nullptr;
   pa.bits_part = reinterpret_cast<unsigned long long*>(b + y.bits_part);
+  pa.lab = pa.placement == 2 ? reinterpret_cast<uint32_t*>(b + y.lab) : nullptr;
 }
 
 // Arguments of fused pass g, reading cur and writing other.
@@ -610,12 +614,14 @@ int enqueue_call(HostPlan& hp, void* X, void* Y, void* plan_area, uint64_t seed,
     a.key0 = pa.key0;
     a.key1 = pa.key1;
     a.vec_ok = ((uintptr_t)cur % 16 == 0) ? 1u : 0u;
+    a.lab = pa.placement == 2 ? pa.lab : nullptr;
     {
       ProfScope ps(prof ? 2 : -1, st);
-      if (pa.placement) launch_merge_r1(pa, (int)l, cur, other, eb, st);
+      if (pa.placement == 1) launch_merge_r1(pa, (int)l, cur, other, eb, st);
       else launch_merge_pass(a, eb, (uint64_t)lv.nmerge * lv.tpm, st);
     }
-    {
+    if (pa.placement != 2) {
+      // (BalancedShuffle's labels already hold the insertion loop)
       ProfScope ps(prof ? 3 : -1, st);
       launch_patch(pa, (int)l, cur, other, eb, st);
     }

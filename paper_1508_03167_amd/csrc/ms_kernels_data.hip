@@ -812,7 +812,9 @@ __global__ void __launch_bounds__(256) merge_pass_kernel(PassArgs a) {
   if (t0 >= N) return;
   const uint32_t t1 = min(t0 + (uint32_t)T, N);
   const uint32_t len = t1 - t0;
-  const uint32_t P = a.P[a.merge_base + m];
+  // BalancedShuffle: every slot by its final label (the labels hold the
+  // break and the insertion loop)
+  const uint32_t P = a.lab ? N : a.P[a.merge_base + m];
   const uint32_t side = a.side[a.merge_base + m];
   const uint64_t cb = a.chunk_base + (uint64_t)m * a.cpm;
   auto r0c = [&](uint32_t t) -> uint32_t {
@@ -837,10 +839,17 @@ __global__ void __launch_bounds__(256) merge_pass_kernel(PassArgs a) {
     }
   }
   const uint32_t nblk = (len + 127) / 128;
+  static_assert((1u << kChunkLog) % (uint32_t)T == 0, "a tile lies inside one chunk");
   if ((uint32_t)tid < nblk) {
-    const W4 f = flip_block((t0 >> kGranLog) + tid, m, a.L, Key{a.key0, a.key1});
+    if (a.lab) {
+      const uint32_t* lw = a.lab + ((cb + (t0 >> kChunkLog)) << 10) + ((t0 >> 5) & 1023u);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) Wd[4 * tid + k] = f.w[k];
+      for (int k = 0; k < 4; ++k) Wd[4 * tid + k] = lw[4 * tid + k];
+    } else {
+      const W4 f = flip_block((t0 >> kGranLog) + tid, m, a.L, Key{a.key0, a.key1});
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Wd[4 * tid + k] = f.w[k];
+    }
   }
   __syncthreads();
   const uint32_t nw = nblk * 4;

@@ -137,6 +137,79 @@ __device__ __forceinline__ void zc_body(const PlanArgs& pa, uint64_t c) {
 }
 __global__ void __launch_bounds__(256) zc_kernel(PlanArgs pa) { zc_body(pa, (uint64_t)blockIdx.x * 256 + threadIdx.x); }
 
+// ---------------------------------------------------------------------------
+// BalancedShuffle (Section 2): the word of each merge is the side labels
+// Algorithm 2 leaves when it merges 0^n1 1^n2 -- label t is coin flip t for
+// t < P, the side that is left for t >= P (B if A ran out, else A), and
+// then the insertion loop permutes the labels as it permutes elements.  The
+// plan writes those labels (one bit per slot, at the slot's chunk and bit
+// position), lets the insertion-loop resolution overwrite the slots it
+// moves, and counts the zeros again; the pass reads the labels.
+// ---------------------------------------------------------------------------
+// The label of slot x before the insertion loop.
+__device__ __forceinline__ uint32_t bal_label0(const PlanArgs& pa, uint32_t L, uint32_t m, uint32_t P,
+                                               uint32_t side, uint32_t x) {
+  if (x >= P) return side == 0 ? 1u : 0u;
+  const W4 f = flip_block(x >> kGranLog, m, L, Key{pa.key0, pa.key1});
+  return (pick(f, (x >> 5) & 3) >> (x & 31)) & 1u;
+}
+
+// Word of slot t of merge m (level lv) in the label array.
+__device__ __forceinline__ uint64_t bal_word(const HbmLevel& lv, uint32_t m, uint32_t t) {
+  return ((lv.chunk_base + (uint64_t)m * lv.cpm + (t >> kChunkLog)) << 10) + ((t >> 5) & 1023u);
+}
+
+__device__ __forceinline__ void bal_set(const PlanArgs& pa, const HbmLevel& lv, uint32_t m, uint32_t t, uint32_t v) {
+  uint32_t* w = pa.lab + bal_word(lv, m, t);
+  const uint32_t bit = 1u << (t & 31);
+  if (v) atomicOr(w, bit);
+  else atomicAnd(w, ~bit);
+}
+
+// One workgroup per chunk: the labels before the insertion loop.
+__global__ void __launch_bounds__(256) bal_words_kernel(PlanArgs pa) {
+  const uint64_t chunk = blockIdx.x;
+  const HbmLevel& lv = pa.lev[level_of_chunk(pa, chunk)];
+  const uint32_t rel = (uint32_t)(chunk - lv.chunk_base);
+  const uint32_t m = rel / lv.cpm;
+  const uint32_t ch = rel - m * lv.cpm;
+  const uint64_t gm = lv.merge_base + m;
+  const uint32_t P = pa.P[gm];
+  const uint32_t fill = pa.side[gm] == 0 ? ~0u : 0u;
+  const uint32_t g = (ch << kChunkGranLog) + threadIdx.x;
+  const W4 f = flip_block(g, m, lv.L, Key{pa.key0, pa.key1});
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t t0 = (g << kGranLog) + 32u * k;  // slot of bit 0
+    uint32_t w = f.w[k];
+    if (t0 + 32 > P) {
+      const uint32_t keep = P > t0 ? (1u << (P - t0)) - 1u : 0u;  // bits below P
+      w = (w & keep) | (fill & ~keep);
+    }
+    pa.lab[(chunk << 10) + 4u * threadIdx.x + k] = w;
+  }
+}
+
+// Zeros per granule and per chunk of the final labels.
+__global__ void __launch_bounds__(256) bal_count_kernel(PlanArgs pa) {
+  __shared__ uint32_t tmp[8];
+  const uint64_t chunk = blockIdx.x;
+  const uint32_t* w = pa.lab + (chunk << 10) + 4u * threadIdx.x;
+  const uint32_t z = 128u - (uint32_t)(__popc(w[0]) + __popc(w[1]) + __popc(w[2]) + __popc(w[3]));
+  uint32_t total;
+  const uint32_t ex = block_excl_scan<256>(z, tmp, &total);
+  pa.zloc[(chunk << kChunkGranLog) + threadIdx.x] = (uint16_t)ex;
+  if (threadIdx.x == 0) pa.ctot[chunk] = total;
+}
+
+__global__ void __launch_bounds__(256) bal_zc_kernel(PlanArgs pa) {
+  const uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= pa.total_chunks) return;
+  const HbmLevel& lv = pa.lev[level_of_chunk(pa, c)];
+  const uint64_t first = c - (uint32_t)(c - lv.chunk_base) % lv.cpm;
+  pa.zc[c] = pa.zg[c] - pa.zg[first];
+}
+
 // Per merge (one thread each): the chunk holding the (n1+1)-th zero and the
 // one holding the (n2+1)-th one by binary search over the chunk prefixes,
 // the flip inside it, and so the break step P and the side that ran out.
@@ -481,7 +554,8 @@ __device__ __forceinline__ void tail_resolve_body(const PlanArgs& pa, uint64_t w
         src = y;                                   // untouched since C0
         break;
       }
-      out = c0_offset(pa, lv, t.m, t.g, t.P, side, src);
+      if (pa.placement == 2) bal_set(pa, lv, t.m, x, bal_label0(pa, lv.L, t.m, t.P, side, src));
+      else out = c0_offset(pa, lv, t.m, t.g, t.P, side, src);
     }
     if (toff + d < pa.tail_cap) pa.tail_src[toff + d] = out;
   }
@@ -493,7 +567,10 @@ __device__ __forceinline__ void tail_resolve_body(const PlanArgs& pa, uint64_t w
     const uint32_t x = pa.pool_x[e];
     const uint32_t st = pa.pool_step[e];
     uint32_t out = kNone32;
-    if (max_target(pa, t.bb, lv.blog, x, kNone32) == st) out = c0_offset(pa, lv, t.m, t.g, t.P, side, st);
+    if (max_target(pa, t.bb, lv.blog, x, kNone32) == st) {
+      if (pa.placement == 2) bal_set(pa, lv, t.m, x, bal_label0(pa, lv.L, t.m, t.P, side, st));
+      else out = c0_offset(pa, lv, t.m, t.g, t.P, side, st);
+    }
     pa.pool_src[e] = out;
   }
 }
@@ -735,7 +812,15 @@ void launch_plan(const PlanArgs& pa, hipStream_t st) {
   hipLaunchKernelGGL(tail_count_kernel, dim3((uint32_t)pa.total_tail_wgs), dim3(256), 0, st, pa);
   launch_scan(pa.bcnt, pa.total_buckets, pa.part, pa.boff, pa.pool_cap, pa.status, 1u, st);
   hipLaunchKernelGGL(tail_scatter_kernel, dim3((uint32_t)pa.total_tail_wgs), dim3(256), 0, st, pa);
+  if (pa.placement == 2)
+    hipLaunchKernelGGL(bal_words_kernel, dim3((uint32_t)pa.total_chunks), dim3(256), 0, st, pa);
   hipLaunchKernelGGL(tail_resolve_kernel, dim3((uint32_t)pa.total_tail_wgs), dim3(256), 0, st, pa);
+  if (pa.placement == 2) {
+    // the passes rank slots among the final labels
+    hipLaunchKernelGGL(bal_count_kernel, dim3((uint32_t)pa.total_chunks), dim3(256), 0, st, pa);
+    launch_scan(pa.ctot, pa.total_chunks, pa.part, pa.zg, ~0ull, pa.status, 0u, st);
+    hipLaunchKernelGGL(bal_zc_kernel, dim3((uint32_t)((pa.total_chunks + 255) / 256)), dim3(256), 0, st, pa);
+  }
   if (pa.tail_xsrc)
     hipLaunchKernelGGL(trace_bounds_kernel, dim3((uint32_t)(pa.total_tail_wgs + (pa.total_bnd + 255) / 256)), dim3(256),
                        0, st, pa);

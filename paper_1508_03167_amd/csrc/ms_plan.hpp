@@ -60,7 +60,8 @@ struct PlanArgs {
   uint32_t c;             // levels
   uint32_t lds_levels;    // levels run inside the leaf kernel
   uint32_t nlev;          // HBM levels: L = lds_levels+1 .. c
-  uint32_t placement;     // 0: stable interleave; 1: in-place swaps of the printed Merge listing
+  uint32_t placement;     // 0: stable interleave; 1: in-place swaps of the printed Merge listing;
+                          // 2: BalancedShuffle (interleave by the final side labels)
   uint32_t key0, key1;    // seed
   uint64_t total_chunks;
   uint64_t total_merges;
@@ -77,6 +78,7 @@ struct PlanArgs {
   uint8_t* side;          // per merge: 0 = A ran out first, 1 = B ran out first
   uint32_t* kcnt;         // per merge: insertion steps N - P
   uint32_t* toff;         // per merge (+1): exclusive prefix of kcnt
+  uint32_t* lab;          // placement 2: per chunk, 1024 words of final side labels (bit t of a merge)
   uint32_t* tail_src;     // per insertion step i: input offset of slot i's final value, or ~0
   uint32_t* bcnt;         // per bucket: target entries (step i, slot j_i < i)
   uint32_t* bfill;        // per bucket: fill cursor
@@ -129,6 +131,7 @@ struct PassArgs {
   const uint8_t* side;
   uint32_t key0, key1;
   uint32_t vec_ok;  // base pointer 16-byte aligned
+  const uint32_t* lab;  // BalancedShuffle: the level's final side labels (else null: coin flips)
 };
 
 struct GroupArgs {
