@@ -69,19 +69,41 @@ def valu_issue_from_profiles(kernel_class: str):
     return round(d[kernel_class]["valu_issue_frac"], 3)
 
 
-def cpu_baseline(n_log2: int):
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n_log2: int, single_log2: int = 25):
+    """The oracle on this host's cores: one MergeShuffle of a uint32 identity
+    array of 2^n_log2 elements (half the GPU step's size, so that the run takes
+    about 10 s on 16 cores) with OpenMP over the blocks and over the merges of
+    each level, and a single-thread leg on 2^single_log2 elements (about the
+    same time on one core)."""
     from oracle import oracle as O
 
     threads = max(1, min(os.cpu_count() or 1, 64))
-    n = 1 << n_log2
     O.build(force=False)
+    n = 1 << n_log2
     t = time.perf_counter()
     O.permutation(n, 4096, 7, threads=threads)
     dt = time.perf_counter() - t
+    n1 = 1 << single_log2
+    t = time.perf_counter()
+    O.permutation(n1, 4096, 7, threads=1)
+    dt1 = time.perf_counter() - t
     return {"value": round(n / dt / 1e9, 4), "unit": "Gelem/s", "cores": threads, "kind": "oracle",
+            "cpu": _cpu_model(),
             "sample": f"one MergeShuffle of a uint32 identity array, n=2^{n_log2}, seed 7, cutoff 4096 "
-                      f"(the GPU step's procedure at 1/{1 << max(0, 30 - n_log2)} of its size), {dt:.2f} s, "
-                      f"OpenMP over the blocks and over the merges of a level"}
+                      f"(the GPU step's procedure at 1/{1 << max(0, 30 - n_log2)} of its size, so the run stays "
+                      f"near 10 s), {dt:.2f} s, OpenMP over the blocks and over the merges of a level",
+            "single_thread": {"value": round(n1 / dt1 / 1e9, 4), "unit": "Gelem/s", "cores": 1,
+                              "sample": f"n=2^{single_log2}, seed 7, cutoff 4096, {dt1:.2f} s"}}
 
 
 def bench_batched(M, torch, reps: int = 5, count: int = 4096, seed: int = 3, tune: bool = True):
