@@ -484,8 +484,39 @@ __device__ __forceinline__ void pass_body(const GroupArgs& a, uint32_t tile) {
     R* dstR = reinterpret_cast<R*>(dst);
     // level li is depth LAM-1-li of the tree (breadth first: the top first)
     const uint32_t e0 = uniform_u32(td.dep_tb[LAM - 1 - li]);
-    const uint32_t ng = 8u * (uniform_u32(td.dep_tb[LAM - li]) - e0);
-    for (uint32_t q = tid; q < ng; q += NT) {
+    const uint32_t ne = uniform_u32(td.dep_tb[LAM - li]) - e0;
+    if constexpr (sizeof(E) == 4) {
+      // groups of 8 slots (a quarter of a flip word): one entry read and one
+      // pair of counts per 8 slots
+      const uint32_t* src4 = reinterpret_cast<const uint32_t*>(src);
+      for (uint32_t q = tid; q < 4u * ne; q += NT) {
+        const uint2 t = td.tab[e0 + (q >> 2)];
+        const uint32_t G = 32u + 8u * q;
+        const uint32_t sh = 8u * (q & 3u);
+        const uint32_t lo = (1u << sh) - 1u;
+        // byte offsets of the next A and B sources
+        uint32_t za = 4u * ((t.y & 0xFFFFu) + (uint32_t)__popc(~t.x & lo));
+        uint32_t ob = 4u * ((t.y >> 16) + (uint32_t)__popc(t.x & lo));
+        const uint32_t b8 = t.x >> sh;
+        const char* srcb = reinterpret_cast<const char*>(src4);
+        uint32_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          // all ones on a 1 flip: take B at ob, else A at za (the mask kept
+          // opaque so that the choice stays one bit select)
+          uint32_t msk = (uint32_t)__builtin_amdgcn_sbfe((int)b8, (uint32_t)j, 1u);
+          asm volatile("" : "+v"(msk));
+          const uint32_t m4 = msk << 2;
+          v[j] = *reinterpret_cast<const uint32_t*>(srcb + ((ob & msk) | (za & ~msk)));
+          za += 4u + m4;
+          ob -= m4;
+        }
+        uint4* d4 = reinterpret_cast<uint4*>(&dst[G]);
+        d4[0] = make_uint4(v[0], v[1], v[2], v[3]);
+        d4[1] = make_uint4(v[4], v[5], v[6], v[7]);
+      }
+    } else
+    for (uint32_t q = tid; q < 8u * ne; q += NT) {
       const uint2 t = td.tab[e0 + (q >> 3)];
       const uint32_t G = 32u + 4u * q;
       const uint32_t s = G & 31u;
@@ -502,20 +533,11 @@ __device__ __forceinline__ void pass_body(const GroupArgs& a, uint32_t tile) {
         za += 1u + msk;
         ob -= msk;
       }
-      if constexpr (sizeof(E) == 4) {
-        uint4 o;
-        o.x = reinterpret_cast<const uint32_t*>(src)[fr[0]];
-        o.y = reinterpret_cast<const uint32_t*>(src)[fr[1]];
-        o.z = reinterpret_cast<const uint32_t*>(src)[fr[2]];
-        o.w = reinterpret_cast<const uint32_t*>(src)[fr[3]];
-        *reinterpret_cast<uint4*>(&dst[G]) = o;
-      } else {
-        const R a0 = srcR[fr[0]], a1 = srcR[fr[1]], a2 = srcR[fr[2]], a3 = srcR[fr[3]];
-        dstR[G] = a0;
-        dstR[G + 1] = a1;
-        dstR[G + 2] = a2;
-        dstR[G + 3] = a3;
-      }
+      const R a0 = srcR[fr[0]], a1 = srcR[fr[1]], a2 = srcR[fr[2]], a3 = srcR[fr[3]];
+      dstR[G] = a0;
+      dstR[G + 1] = a1;
+      dstR[G + 2] = a2;
+      dstR[G + 3] = a3;
     }
     __syncthreads();
     // insertion-loop slots of this level inside the tile
