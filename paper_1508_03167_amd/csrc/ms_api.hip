@@ -25,12 +25,12 @@
 namespace ms {
 void launch_group(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st);
 int group_tile(uint32_t eb);
-void launch_pass_group(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st);
-int pass_group_tile(uint32_t eb);
+void launch_pass_group(const GroupArgs& a, int lam, uint32_t eb, uint32_t T, uint64_t grid, hipStream_t st);
+int pass_group_tile(uint32_t eb, uint64_t n);
 void launch_pass_group_multi(const GroupArgs* jobs, const uint32_t* tpre, uint32_t njobs, uint32_t ntiles, int lam,
                              uint32_t eb, hipStream_t st);
-uint32_t pass_desc_words(uint32_t eb, int lam);
-void launch_pass_desc(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st);
+uint32_t pass_desc_words(uint32_t eb, uint32_t T, int lam);
+void launch_pass_desc(const GroupArgs& a, int lam, uint32_t eb, uint32_t T, uint64_t grid, hipStream_t st);
 void launch_pass_desc_multi(const GroupArgs* jobs, const uint32_t* tpre, uint32_t njobs, uint32_t ntiles, int lam,
                             uint32_t eb, hipStream_t st);
 void launch_plan(const PlanArgs& pa, hipStream_t st);
@@ -85,10 +85,10 @@ bool pass_tree() {
   }();
   return v;
 }
-int fused_tile(uint32_t eb) { return pass_tree() ? group_tile(eb) : pass_group_tile(eb); }
-void launch_fused(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st) {
+int fused_tile(uint32_t eb, uint64_t n) { return pass_tree() ? group_tile(eb) : pass_group_tile(eb, n); }
+void launch_fused(const GroupArgs& a, int lam, uint32_t eb, uint32_t T, uint64_t grid, hipStream_t st) {
   if (pass_tree()) launch_group(a, lam, eb, grid, st);
-  else launch_pass_group(a, lam, eb, grid, st);
+  else launch_pass_group(a, lam, eb, T, grid, st);
 }
 void launch_fused_multi(const GroupArgs* jobs, const uint32_t* tpre, uint32_t njobs, uint32_t ntiles, int lam,
                         uint32_t eb, hipStream_t st) {
@@ -257,7 +257,7 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
   }
   uint64_t all_bnd = 0, all_desc = 0;
   if (hp.fused) {
-    const uint32_t Tg = (uint32_t)fused_tile(eb);
+    const uint32_t Tg = (uint32_t)fused_tile(eb, n);
     tiles = 0;
     for (uint32_t g = 0; g < hp.ngroup; ++g) {
       const HbmLevel& top = pa.lev[hp.gfirst[g] + hp.glam[g] - 1];
@@ -268,7 +268,7 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
       gi.tpm = (top.nmax + Tg - 1) / Tg;
       gi.bnd_first = all_bnd;
       // the table pass reads one descriptor per tile, built by the plan
-      hp.gdesc_words[g] = pass_tree() ? 0u : pass_desc_words(eb, (int)gi.lam);
+      hp.gdesc_words[g] = pass_tree() ? 0u : pass_desc_words(eb, Tg, (int)gi.lam);
       hp.gdesc_first[g] = all_desc;
       all_desc += (uint64_t)top.nmerge * gi.tpm * hp.gdesc_words[g];
       for (uint32_t k = 0; k < gi.lam; ++k) {
@@ -558,7 +558,7 @@ int enqueue_call(HostPlan& hp, void* X, void* Y, void* plan_area, uint64_t seed,
           void* o = c == X ? Y : X;
           const GroupInfo& gi = pa.grp[g];
           const GroupArgs ga = group_args(hp, g, c, o);
-          launch_pass_desc(ga, (int)gi.lam, eb, (uint64_t)pa.lev[gi.lf + gi.lam - 1].nmerge * gi.tpm,
+          launch_pass_desc(ga, (int)gi.lam, eb, gi.T, (uint64_t)pa.lev[gi.lf + gi.lam - 1].nmerge * gi.tpm,
                            fork ? plan_st : st);
           c = o;
         }
@@ -590,7 +590,7 @@ int enqueue_call(HostPlan& hp, void* X, void* Y, void* plan_area, uint64_t seed,
     const HbmLevel& top = pa.lev[gi.lf + gi.lam - 1];
     {
       ProfScope ps(prof ? 2 : -1, st);
-      launch_fused(ga, (int)gi.lam, eb, (uint64_t)top.nmerge * gi.tpm, st);
+      launch_fused(ga, (int)gi.lam, eb, gi.T, (uint64_t)top.nmerge * gi.tpm, st);
     }
     cur = other;
   }

@@ -632,23 +632,39 @@ __global__ void __launch_bounds__(kDescThreads) pass_desc_multi_kernel(const Gro
 }
 
 // Tile shapes (slots per tile, threads per workgroup) per element size; the
-// first is the default, MS_PASS_TILE=<slots> picks another.  A tuning choice
-// only: the permutation does not depend on it.
+// first is the default, MS_PASS_TILE=<slots> picks another.  4-byte arrays of
+// 2^26 elements or more take 8192-slot tiles of 1024 threads: half the tiles
+// of the default, so half the descriptors for the plan to build (measured at
+// 2^30: 27.3 against 27.9 ms per shuffle, the passes themselves 6 % slower).
+// A tuning choice only: the permutation does not depend on it.
 struct TileShape {
   int T, NT;
 };
-static const TileShape kShapes4[] = {{3584, 512}, {4096, 512}, {2048, 256}, {8192, 1024}};
+static const TileShape kShapes4[] = {{3584, 512}, {4096, 512}, {2048, 256}, {8192, 1024}, {7168, 1024}};
 static const TileShape kShapes8[] = {{2048, 512}, {1792, 512}, {1024, 256}, {4096, 1024}};
 static const TileShape kShapes16[] = {{1024, 256}, {640, 256}, {512, 128}, {2048, 512}};
+constexpr uint64_t kBigTileN = 1ull << 26;
 
-static TileShape shape_for(uint32_t eb) {
+static int shape_count(uint32_t eb) { return eb == 4 ? (int)(sizeof kShapes4 / sizeof kShapes4[0]) : 4; }
+static const TileShape* shapes_of(uint32_t eb) { return eb == 4 ? kShapes4 : eb == 8 ? kShapes8 : kShapes16; }
+
+// The tile of a pass over an array of n elements of eb bytes.
+int pass_group_tile(uint32_t eb, uint64_t n) {
   static const int want = [] {
     const char* e = getenv("MS_PASS_TILE");
     return e ? atoi(e) : 0;
   }();
-  const TileShape* t = eb == 4 ? kShapes4 : eb == 8 ? kShapes8 : kShapes16;
-  for (int i = 0; i < 4; ++i)
-    if (t[i].T == want) return t[i];
+  const TileShape* t = shapes_of(eb);
+  for (int i = 0; i < shape_count(eb); ++i)
+    if (t[i].T == want) return t[i].T;
+  if (eb == 4 && n >= kBigTileN) return 8192;
+  return t[0].T;
+}
+
+static TileShape shape_of(uint32_t eb, uint32_t T) {
+  const TileShape* t = shapes_of(eb);
+  for (int i = 0; i < shape_count(eb); ++i)
+    if ((uint32_t)t[i].T == T) return t[i];
   return t[0];
 }
 
@@ -662,12 +678,13 @@ static void with_lam(int lam, F& f) {
 }
 
 template <typename F>
-static void with_shape(uint32_t eb, int lam, F& f) {
-  const TileShape sh = shape_for(eb);
+static void with_shape(uint32_t eb, uint32_t T, int lam, F& f) {
+  const TileShape sh = shape_of(eb, T);
   if (eb == 4) {
     if (sh.T == 4096) with_lam<uint32_t, 4096, 512>(lam, f);
     else if (sh.T == 2048) with_lam<uint32_t, 2048, 256>(lam, f);
     else if (sh.T == 8192) with_lam<uint32_t, 8192, 1024>(lam, f);
+    else if (sh.T == 7168) with_lam<uint32_t, 7168, 1024>(lam, f);
     else with_lam<uint32_t, 3584, 512>(lam, f);
   } else if (eb == 8) {
     if (sh.T == 1792) with_lam<uint64_t, 1792, 512>(lam, f);
@@ -681,8 +698,6 @@ static void with_shape(uint32_t eb, int lam, F& f) {
     else with_lam<uint4, 1024, 256>(lam, f);
   }
 }
-
-int pass_group_tile(uint32_t eb) { return shape_for(eb).T; }
 
 struct DescWordsF {
   uint32_t w = 0;
@@ -718,34 +733,35 @@ struct LaunchPassMultiF {
   }
 };
 
-uint32_t pass_desc_words(uint32_t eb, int lam) {
+uint32_t pass_desc_words(uint32_t eb, uint32_t T, int lam) {
   DescWordsF f;
-  with_shape(eb, lam, f);
+  with_shape(eb, T, lam, f);
   return f.w;
 }
 
-void launch_pass_group(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st) {
+void launch_pass_group(const GroupArgs& a, int lam, uint32_t eb, uint32_t T, uint64_t grid, hipStream_t st) {
   LaunchPassF f{&a, grid, st, false};
-  with_shape(eb, lam, f);
+  with_shape(eb, T, lam, f);
 }
 
-void launch_pass_desc(const GroupArgs& a, int lam, uint32_t eb, uint64_t grid, hipStream_t st) {
+void launch_pass_desc(const GroupArgs& a, int lam, uint32_t eb, uint32_t T, uint64_t grid, hipStream_t st) {
   LaunchPassF f{&a, grid, st, true};
-  with_shape(eb, lam, f);
+  with_shape(eb, T, lam, f);
 }
 
+// (batched arrays hold at most 2^21 elements: the default tile)
 void launch_pass_group_multi(const GroupArgs* jobs, const uint32_t* tpre, uint32_t njobs, uint32_t ntiles, int lam,
                              uint32_t eb, hipStream_t st) {
   if (!ntiles) return;
   LaunchPassMultiF f{jobs, tpre, njobs, ntiles, st, false};
-  with_shape(eb, lam, f);
+  with_shape(eb, (uint32_t)pass_group_tile(eb, 0), lam, f);
 }
 
 void launch_pass_desc_multi(const GroupArgs* jobs, const uint32_t* tpre, uint32_t njobs, uint32_t ntiles, int lam,
                             uint32_t eb, hipStream_t st) {
   if (!ntiles) return;
   LaunchPassMultiF f{jobs, tpre, njobs, ntiles, st, true};
-  with_shape(eb, lam, f);
+  with_shape(eb, (uint32_t)pass_group_tile(eb, 0), lam, f);
 }
 
 }  // namespace ms

@@ -49,7 +49,7 @@ for n, seed, eb in [(70001, 3, 4), ((1 << 20) + 3, 4, 4), (3_000_017, 5, 4), (30
 
 KNOBS = [({"MS_LEAF_BIG": "1"}, {}), ({"MS_PASS_IMPL": "tree"}, {}),
          ({"MS_PASS_IMPL": "tree", "MS_GROUP_TILE": "2048"}, {})] + [
-    ({"MS_PASS_TILE": str(t)}, {}) for t in (4096, 2048, 8192, 1792, 1024, 640, 512)] + [
+    ({"MS_PASS_TILE": str(t)}, {}) for t in (4096, 2048, 8192, 7168, 1792, 1024, 640, 512)] + [
     ({"MS_PASS_VARIANT": str(v)}, {"one_level_passes": True}) for v in range(1, 6)]
 
 
