@@ -369,6 +369,7 @@ def main():
     n = 1 << args.n_log2
     x = torch.arange(n, dtype=torch.int32, device="cuda:0")
     plan = M.plan(n, 4)
+    plan_tile = 8192 if n >= (1 << 26) and not os.environ.get("MS_PASS_TILE") else int(os.environ.get("MS_PASS_TILE", 3584))
     for _ in range(args.warmup):
         M.shuffle_(x, args.seed)
     torch.cuda.synchronize()
@@ -393,7 +394,8 @@ def main():
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": traffic_from_profiles("merge_pass_n2^30_u32"),
-                "kernel": "group_kernel<uint32_t,4096,levels>", "avg_launch_ms": round(avg, 4),
+                "kernel": f"pass_kernel<uint32_t,{plan_tile},levels,{1024 if plan_tile == 8192 else 512}>",
+                "avg_launch_ms": round(avg, 4),
                 "launches": cnt_cls["merge_pass"],
                 "levels_per_launch": round(plan["hbm_levels"] * args.steps / launches, 3),
                 "alg_bytes_per_launch": 2 * n * 4,

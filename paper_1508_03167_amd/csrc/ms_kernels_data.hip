@@ -62,17 +62,29 @@ __device__ __forceinline__ uint32_t get16(uint32_t packed, int half) { return (p
 // else by ok runs straight through.  The opaque copy of lt keeps the
 // compiler from computing every slot's address once and holding it across
 // phases.
-template <int SPT, typename Body>
+template <int SPT, typename Body, int I0 = 0, int I1 = SPT>
 __device__ __forceinline__ void for_slots(uint32_t lt, uint32_t tpl, uint32_t lb, uint32_t b, uint32_t dummy,
                                           Body&& body) {
   uint32_t x0 = lt;
   asm volatile("" : "+v"(x0));
 #pragma unroll
-  for (int i = 0; i < SPT; ++i) {
+  for (int i = I0; i < I1; ++i) {
     const uint32_t x = x0 + tpl * (uint32_t)i;
     const bool ok = x < b;
     body(i, x, ok ? lb + x : dummy, ok);
   }
+}
+
+// The same over the slots in two halves, each read completely before it is
+// written (half the registers of reading every slot first).
+template <int SPT, typename Read, typename Write>
+__device__ __forceinline__ void for_slots_rw(uint32_t lt, uint32_t tpl, uint32_t lb, uint32_t b, uint32_t dummy,
+                                             Read&& rd, Write&& wr) {
+  constexpr int H = (SPT + 1) / 2;
+  for_slots<SPT, Read&, 0, H>(lt, tpl, lb, b, dummy, rd);
+  for_slots<SPT, Write&, 0, H>(lt, tpl, lb, b, dummy, wr);
+  for_slots<SPT, Read&, H, SPT>(lt, tpl, lb, b, dummy, rd);
+  for_slots<SPT, Write&, H, SPT>(lt, tpl, lb, b, dummy, wr);
 }
 
 __device__ __forceinline__ uint32_t set16(uint32_t packed, int half, uint32_t v) {
@@ -202,10 +214,8 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uin
   // and its results are not used.
   {
     uint32_t v[SPT];
-    for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t w, bool) { v[i] = W[w]; });
-    for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t r, uint32_t w, bool) {
-      W[w] = ((r >= 1 ? v[i] : NONE) << 16) | NONE;
-    });
+    for_slots_rw<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t w, bool) { v[i] = W[w]; },
+                      [&](int i, uint32_t r, uint32_t w, bool) { W[w] = ((r >= 1 ? v[i] : NONE) << 16) | NONE; });
   }
   __syncthreads();
   constexpr int ITER = 4 * BPT;  // pushes per lane, at most
@@ -257,19 +267,26 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uin
   {
     // (every target is read before the first write; the writes touch the
     // heads of targets and the links of this lane's own steps)
-    uint32_t y[ITER];
+    constexpr int H = (ITER + 1) / 2;
 #pragma unroll
-    for (int t = 0; t < ITER; ++t) {
-      const uint32_t r = r0 + lpp * t;
-      y[t] = W[r >= 1 && r < r1 ? lb + r : dummy] >> 16;
-    }
+    for (int h0 = 0; h0 < ITER; h0 += H) {
+      uint32_t y[H];
 #pragma unroll
-    for (int t = 0; t < ITER; ++t) {
-      const uint32_t r = r0 + lpp * t;
-      const bool ok = r >= 1 && r < r1;
-      const uint32_t old = get16(OLD[t >> 1], t & 1);
-      HED(ok && old == NONE ? lb + y[t] : dummy) = (uint16_t)(r != y[t] ? r : NONE);
-      LNK(ok ? lb + r : dummy) = (uint16_t)(y[t] | NOLATER);
+      for (int k = 0; k < H; ++k) {
+        const int t = h0 + k;
+        const uint32_t r = r0 + lpp * t;
+        y[k] = t < ITER ? W[r >= 1 && r < r1 ? lb + r : dummy] >> 16 : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        const int t = h0 + k;
+        if (t >= ITER) break;
+        const uint32_t r = r0 + lpp * t;
+        const bool ok = r >= 1 && r < r1;
+        const uint32_t old = get16(OLD[t >> 1], t & 1);
+        HED(ok && old == NONE ? lb + y[k] : dummy) = (uint16_t)(r != y[k] ? r : NONE);
+        LNK(ok ? lb + r : dummy) = (uint16_t)(y[k] | NOLATER);
+      }
     }
   }
   __syncthreads();
@@ -279,23 +296,31 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uin
     // Pushes onto one slot came in increasing step order; a lane that sees
     // otherwise reports it (bit 3), the lists are then unordered.
     bool unordered = false;
-    uint32_t wv[ITER];
+    constexpr int H = (ITER + 1) / 2;
 #pragma unroll
-    for (int t = 0; t < ITER; ++t) {
-      const uint32_t r = r0 + lpp * t;
-      const uint32_t old = get16(OLD[t >> 1], t & 1);
-      const bool ok = r >= 1 && r < r1 && old != NONE;
-      wv[t] = W[ok ? lb + old : dummy];
-    }
+    for (int h0 = 0; h0 < ITER; h0 += H) {
+      uint32_t wv[H];
 #pragma unroll
-    for (int t = 0; t < ITER; ++t) {
-      const uint32_t r = r0 + lpp * t;
-      const uint32_t old = get16(OLD[t >> 1], t & 1);
-      const bool ok = r >= 1 && r < r1 && old != NONE;
-      unordered |= ok && old > r;
-      const uint32_t lk = wv[t] >> 16, hd = wv[t] & 0xFFFFu;
-      // head (low half) and link (high half) of the old step's word
-      W[ok ? lb + old : dummy] = (r << 16) | (lk == (old | NOLATER) ? r : hd);
+      for (int k = 0; k < H; ++k) {
+        const int t = h0 + k;
+        if (t >= ITER) break;
+        const uint32_t r = r0 + lpp * t;
+        const uint32_t old = get16(OLD[t >> 1], t & 1);
+        const bool ok = r >= 1 && r < r1 && old != NONE;
+        wv[k] = W[ok ? lb + old : dummy];
+      }
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        const int t = h0 + k;
+        if (t >= ITER) break;
+        const uint32_t r = r0 + lpp * t;
+        const uint32_t old = get16(OLD[t >> 1], t & 1);
+        const bool ok = r >= 1 && r < r1 && old != NONE;
+        unordered |= ok && old > r;
+        const uint32_t lk = wv[k] >> 16, hd = wv[k] & 0xFFFFu;
+        // head (low half) and link (high half) of the old step's word
+        W[ok ? lb + old : dummy] = (r << 16) | (lk == (old | NOLATER) ? r : hd);
+      }
     }
     if (unordered) atomicOr(status, 8u);
   }
@@ -319,16 +344,23 @@ __device__ __forceinline__ void leaf_fy_sources(uint16_t* head, uint32_t lb, uin
   {
     uint64_t live = 0;
     {
+      // in two halves of the slots, each: every head, then every head's
+      // head, then the links
       uint32_t t[SPT], tt[SPT];
-      for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t w, bool) { t[i] = HED(w); });
-      for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t, bool ok) {
-        tt[i] = HED(ok && t[i] != NONE ? lb + t[i] : dummy);
-      });
-      for_slots<SPT>(lt, tpl, lb, b, dummy, [&](int i, uint32_t, uint32_t w, bool ok) {
+      auto rd1 = [&](int i, uint32_t, uint32_t w, bool) { t[i] = HED(w); };
+      auto rd2 = [&](int i, uint32_t, uint32_t, bool ok) { tt[i] = HED(ok && t[i] != NONE ? lb + t[i] : dummy); };
+      auto wr = [&](int i, uint32_t, uint32_t w, bool ok) {
         const bool two = ok && t[i] != NONE && tt[i] != NONE;
         LNK(w) = (uint16_t)(two ? tt[i] : t[i]);
         live |= (uint64_t)two << i;
-      });
+      };
+      constexpr int H = (SPT + 1) / 2;
+      for_slots<SPT, decltype(rd1)&, 0, H>(lt, tpl, lb, b, dummy, rd1);
+      for_slots<SPT, decltype(rd2)&, 0, H>(lt, tpl, lb, b, dummy, rd2);
+      for_slots<SPT, decltype(wr)&, 0, H>(lt, tpl, lb, b, dummy, wr);
+      for_slots<SPT, decltype(rd1)&, H, SPT>(lt, tpl, lb, b, dummy, rd1);
+      for_slots<SPT, decltype(rd2)&, H, SPT>(lt, tpl, lb, b, dummy, rd2);
+      for_slots<SPT, decltype(wr)&, H, SPT>(lt, tpl, lb, b, dummy, wr);
     }
     while (live) {
       const int q = __builtin_ctzll(live);
@@ -459,7 +491,10 @@ __device__ __forceinline__ void copy_block(E* lds, E* glob, uint32_t cnt) {
   const uint32_t h = min(cnt, (uint32_t)(((16u - mis) & 15u) / sizeof(E)));
   const uint32_t groups = (cnt - h) / PER;
   const uint32_t tail0 = h + groups * PER;
-  const uint32_t tid = threadIdx.x;
+  // (an opaque copy of the thread index: the load and the store at the two
+  // ends of the leaf kernel compute their addresses each, none held between)
+  uint32_t tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
   if (tid < h) {
     if (TO_LDS) lds[tid] = glob[tid];
     else glob[tid] = lds[tid];
