@@ -286,7 +286,9 @@ def bench_served(M, torch, count: int = 20000, seed: int = 5, load: float = 0.7,
     served by the continuous-batching server: the admitted requests go, in
     arrival order, into the next batched call on a free stream (up to
     `inflight` batches on the device; a batch closes before it would exceed
-    `batch_elems` elements, so a large request goes alone).  The same stream
+    `batch_elems` elements, so a large request goes alone, and one large
+    request is on the device at a time, passed meanwhile by smaller ones).
+    The same stream
     through the plain loop: one ms_shuffle call per request, one at a time,
     same admission.  Capacity is the throughput of the first 2000 requests all
     present at the start, after a warm-up on the first 300."""
@@ -309,10 +311,12 @@ def bench_served(M, torch, count: int = 20000, seed: int = 5, load: float = 0.7,
     def run(rate, k, batched, check=()):
         ex = GpuExecutor(budget, inflight if batched else 1, fill=fill, batched=batched, check=check)
         if batched:
-            r = serve_stream(requests(rate, k), ex, budget, inflight, max_batch_elems=batch_elems)
+            r = serve_stream(requests(rate, k), ex, budget, inflight, max_batch_elems=batch_elems,
+                             max_large_inflight=1)
         else:
             r = serve_stream(requests(rate, k), ex, budget, max_inflight=1, max_batch=1)
         if check:
+            ex.verify()
             r["results_checked_alone"] = len(ex.checked)
             r["results_equal_alone_and_in_mix"] = not ex.mismatches and len(ex.checked) == len(check)
         del ex
@@ -328,7 +332,7 @@ def bench_served(M, torch, count: int = 20000, seed: int = 5, load: float = 0.7,
     return {"workload": f"{count} requests, sizes floor(2^(10+16u)), uint32 or uint64 random values, "
                         f"Poisson arrivals at {load} x measured capacity, HBM budget {budget_gib} GiB, seed {seed}",
             "requests": count, "mean_elements": round(mean_n), "inflight_batches": inflight,
-            "batch_elems_cap": batch_elems,
+            "batch_elems_cap": batch_elems, "large_requests_in_flight": 1,
             "capacity_gelem_s": {"continuous_batching": cap["gelem_s"], "one_call_per_request": cap_plain["gelem_s"]},
             "arrival_rate_req_s": round(rate, 1),
             "continuous_batching": batched, "one_call_per_request": plain}

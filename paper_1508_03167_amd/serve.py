@@ -7,7 +7,8 @@ a call of its size needs -- and refuses outright a request that alone exceeds
 the budget.  Admitted requests wait in arrival order; whenever one of the
 server's `max_inflight` slots (one stream each) is free, the admitted
 requests not yet launched go, in arrival order and up to an element cap,
-into one batched call on that slot
+into one batched call on that slot (optionally, requests above the cap
+run at most a few at a time, passed meanwhile by smaller ones)
 (ms_shuffle_batched_seeds: each request shuffled with its own seed), so
 requests that arrive while others run join the next batch and overlap the
 batches already on the device.  Completion is seen by polling an event per
@@ -54,7 +55,7 @@ class Server:
     """The admission / batching / completion logic of the server."""
 
     def __init__(self, executor, hbm_budget: int, max_inflight: int = 2, max_batch: int = 4096,
-                 max_batch_elems: Optional[int] = None):
+                 max_batch_elems: Optional[int] = None, max_large_inflight: Optional[int] = None):
         if max_inflight < 1:
             raise ValueError("max_inflight must be at least 1")
         self.ex = executor
@@ -65,6 +66,11 @@ class Server:
         # past this (it always takes at least one), so that small requests do
         # not wait for the completion of a large one launched with them
         self.max_batch_elems = max_batch_elems
+        # requests above the element cap ("large") on the device at once: with
+        # a limit, a large request that would exceed it waits and smaller ones
+        # behind it may go first (large requests slow one another down when
+        # they share the device, small ones barely do)
+        self.max_large_inflight = max_large_inflight
         self.used = 0
         self.waiting: collections.deque = collections.deque()   # arrived, not admitted
         self.ready: collections.deque = collections.deque()     # admitted, not launched
@@ -111,18 +117,31 @@ class Server:
                     self.ex.release(r)
                     self.finished.append(r)
 
+    def _large(self, r: Request) -> bool:
+        return self.max_batch_elems is not None and r.n > self.max_batch_elems
+
     def _launch(self, now: float):
         free = [s for s in range(self.max_inflight) if s not in self.inflight]
         while free and self.ready:
-            slot = free.pop(0)
+            large_busy = self.max_large_inflight is not None and sum(
+                1 for _, rs, _ in self.inflight.values() if any(self._large(r) for r in rs)) >= self.max_large_inflight
             reqs = []
             elems = 0
+            keep = collections.deque()
             while self.ready and len(reqs) < self.max_batch:
-                n = self.ready[0].n
-                if reqs and self.max_batch_elems is not None and elems + n > self.max_batch_elems:
+                r = self.ready[0]
+                if large_busy and self._large(r):
+                    keep.append(self.ready.popleft())  # waits for the large slot
+                    continue
+                if reqs and self.max_batch_elems is not None and elems + r.n > self.max_batch_elems:
                     break
-                elems += n
+                elems += r.n
                 reqs.append(self.ready.popleft())
+            keep.extend(self.ready)
+            self.ready = keep
+            if not reqs:
+                break
+            slot = free.pop(0)
             for r in reqs:
                 r.launched = now
                 r.batch = self.batches
@@ -173,9 +192,11 @@ class GpuExecutor:
 
     batched=False launches one ms_shuffle call per request instead (with
     max_batch=1 and one slot, the plain one-call-per-request loop).  For the
-    request ids in `check`, the input is copied before the launch and, once
-    the batch is done, shuffled alone with the request's seed and compared
-    with the result in the mix; `mismatches` lists those that differ."""
+    request ids in `check`, the input is copied before the launch and the
+    result once its batch is done (device copies, no waiting); verify() then
+    shuffles each input alone with the request's seed and compares it with
+    the result from the mix, after the stream, so that checking adds no
+    latency to the requests; `mismatches` lists those that differ."""
 
     poll_is_cheap = True
 
@@ -196,7 +217,8 @@ class GpuExecutor:
         self.scratch_cache = {}
         self.batched = batched
         self.check = set(check)
-        self.saved = {}
+        self.saved = {}      # rid -> (input copy, seed)
+        self.results = {}    # rid -> result copy
         self.checked = []
         self.mismatches = []
 
@@ -219,12 +241,9 @@ class GpuExecutor:
 
     def release(self, r: Request):
         if r.rid in self.saved:
-            before = self.saved.pop(r.rid)
-            self.M.shuffle_(before, r.seed)
-            self.torch.cuda.synchronize()
-            self.checked.append(r.rid)
-            if not bool(self.torch.equal(before, self.view(r))):
-                self.mismatches.append(r.rid)
+            # the batch's event has completed: copy the result before the
+            # range is reused
+            self.results[r.rid] = self.view(r).clone()
         need = -(-r.n * r.elem_bytes // ALIGN) * ALIGN
         self.free.append((r.offset, need))
         self.free.sort()
@@ -249,7 +268,7 @@ class GpuExecutor:
         with torch.cuda.stream(st):
             for r in reqs:
                 if r.rid in self.check:
-                    self.saved[r.rid] = self.view(r).clone()
+                    self.saved[r.rid] = (self.view(r).clone(), r.seed)
         if self.batched:
             self.M.shuffle_batched_seeds_([self.view(r) for r in reqs], [r.seed for r in reqs], stream=st)
         else:
@@ -262,12 +281,29 @@ class GpuExecutor:
     def done(self, ev) -> bool:
         return ev.query()
 
+    def verify(self):
+        """Shuffle each checked input alone and compare it with its result
+        from the mix (call after the stream has been served)."""
+        torch = self.torch
+        torch.cuda.synchronize()
+        for rid, (before, seed) in sorted(self.saved.items()):
+            if rid not in self.results:
+                continue
+            self.M.shuffle_(before, seed)
+            torch.cuda.synchronize()
+            self.checked.append(rid)
+            if not bool(torch.equal(before, self.results[rid])):
+                self.mismatches.append(rid)
+        self.saved.clear()
+        self.results.clear()
+
 
 def serve_stream(requests: List[Request], executor, hbm_budget: int, max_inflight: int = 2,
-                 max_batch: int = 4096, max_batch_elems: Optional[int] = None):
+                 max_batch: int = 4096, max_batch_elems: Optional[int] = None,
+                 max_large_inflight: Optional[int] = None):
     """Run a request stream in real time on the executor; returns summary figures."""
     srv = Server(executor, hbm_budget, max_inflight=max_inflight, max_batch=max_batch,
-                 max_batch_elems=max_batch_elems)
+                 max_batch_elems=max_batch_elems, max_large_inflight=max_large_inflight)
     t0 = time.perf_counter()
 
     def wait(dt):

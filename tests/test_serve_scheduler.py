@@ -155,3 +155,20 @@ def test_element_cap_keeps_small_requests_out_of_large_batches():
     assert ex.launches[2] == [51]
     for b in ex.launches:
         assert len(b) == 1 or sum(1000 for _ in b) <= 1 << 20
+
+
+def test_large_requests_take_turns_and_small_ones_pass_them():
+    # two large requests arrive together with small ones: with one large
+    # request on the device at a time, the second large one waits for the
+    # first to finish while the small ones behind it are launched
+    reqs = [Request(0, 1 << 24, 4, 1, 0.0), Request(1, 1 << 24, 4, 2, 0.0)]
+    reqs += [Request(2 + i, 1000, 4, 10 + i, 0.0) for i in range(20)]
+    clock = SimClock()
+    ex = FakeExecutor(clock, 8 << 30)
+    srv = Server(ex, 8 << 30, max_inflight=3, max_batch_elems=1 << 20, max_large_inflight=1)
+    done, rej = srv.run(reqs, clock.now, clock.wait)
+    r = {q.rid: q for q in done}
+    assert len(done) == 22 and not rej
+    assert r[1].launched >= r[0].done
+    assert all(r[2 + i].launched < r[1].launched for i in range(20))
+    assert ex.launches[0] == [0]
