@@ -667,33 +667,37 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
     // per-slot addresses of every level out of the level loop.
     uint32_t tv = (uint32_t)tid;
     asm volatile("" : "+v"(tv));
-    const float inv_msize = (float)nm / (float)cnt;
     // slots go by groups of 4 consecutive slots (group q of this thread:
     // slots 4 * (tid + q * NT) + j); a group inside one merge and before its
     // break step shares one flip word pair: with o_j the ones among its
-    // first j flips, slot j takes B at n1 + t0 - r0 + o_j or A at r0 + j - o_j
+    // first j flips, slot j takes B at n1 + t0 - r0 + o_j or A at r0 + j - o_j.
+    // A thread's groups go up through the slots, so its merge only moves
+    // forward: the merge's bounds stay in registers until a group passes
+    // its end.
     constexpr int KG = (KS + 3) / 4;
     using R = typename RegOf<E>::type;
     R* dataR = reinterpret_cast<R*>(data);
     R val[4 * KG];
+    uint32_t mm = 0, m0 = mb[0], m1 = mb[1], n1 = mmid[0] - mb[0], P = mP[0] >> 1, wb = maux.wpre[0];
 #pragma unroll
     for (int q = 0; q < KG; ++q) {
       const uint32_t s0 = 4 * (tv + q * NT);
       uint32_t src[4] = {0u, 0u, 0u, 0u};
       if (s0 < cnt) {
-        // merges of a level have sizes within one of each other
-        uint32_t mm = min((uint32_t)((float)s0 * inv_msize), nm - 1);
-        while (mm > 0 && mb[mm] > s0) --mm;
-        while (mm + 1 < nm && mb[mm + 1] <= s0) ++mm;
-        const uint32_t m0 = mb[mm], m1 = mb[mm + 1];
+        while (mm + 1 < nm && m1 <= s0) {
+          ++mm;
+          m0 = m1;
+          m1 = mb[mm + 1];
+          n1 = mmid[mm] - m0;
+          P = mP[mm] >> 1;
+          wb = maux.wpre[mm * W];
+        }
         const uint32_t t0 = s0 - m0;
-        const uint32_t n1 = mmid[mm] - m0;
-        const uint32_t P = mP[mm] >> 1;
         if (s0 + 4 <= m1 && t0 + 4 <= P) {
           const uint32_t w = mm * W + (t0 >> 5);
           const uint32_t wlo = maux.words[w], whi = maux.words[w + 1];
           const uint32_t bp = t0 & 31;
-          const uint32_t r0 = maux.wpre[w] - maux.wpre[mm * W] + (uint32_t)__popc(~wlo & ((1u << bp) - 1u));
+          const uint32_t r0 = maux.wpre[w] - wb + (uint32_t)__popc(~wlo & ((1u << bp) - 1u));
           const uint32_t bits4 = (uint32_t)((((uint64_t)whi << 32) | wlo) >> bp);
           // xb = B's next source and xa + j = A's, moved by the all-ones mask
           // of each 1 flip (kept opaque: a bit select, not compare and select)
