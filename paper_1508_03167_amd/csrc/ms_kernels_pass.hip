@@ -337,6 +337,9 @@ __device__ __forceinline__ void desc_body(const GroupArgs& a, uint32_t tile, uin
 }
 
 // One tile of one fused pass, from its descriptor.
+// slots per thread and step in the 4-byte levels
+constexpr uint32_t kPassGroup4 = 4;
+
 template <typename E, int T, int LAM, int NT>
 __device__ __forceinline__ void pass_body(const GroupArgs& a, uint32_t tile) {
   using S = DescShape<T, LAM>;
@@ -412,48 +415,73 @@ __device__ __forceinline__ void pass_body(const GroupArgs& a, uint32_t tile) {
     stot += pcnt[r];
     ptot += pcnt[NODES + r];
   }
-  // patch e of the ranges from rbeg on: its level (bits 16..), LDS position
-  // (bits 0..15) and pass-input element relative to sMa, or meta = NONE.
-  // Ranges 0..NODES-1 are the windows' insertion steps, NODES..2*NODES-1
-  // their target entries.
-  auto patch_at = [&](int rbeg, uint32_t e, uint32_t& meta) -> uint32_t {
+  // patch e of the ranges from rbeg on: its range, and in `start` the
+  // patches of the range's predecessors.  Ranges 0..NODES-1 are the windows'
+  // insertion steps, NODES..2*NODES-1 their target entries.
+  auto locate = [&](int rbeg, uint32_t e, uint32_t& start) -> int {
     int r = rbeg;
-    uint32_t start = 0;
+    start = 0;
     while (e >= start + pcnt[r]) {
       start += pcnt[r];
       ++r;
     }
-    const int k = r < NODES ? r : r - NODES;
-    const uint32_t* nr = td.node[k];
+    return r;
+  };
+  // a patch of range r with target slot x and source xs: its level (bits
+  // 16..) and LDS position (bits 0..15), or NONE, and in `src` its
+  // pass-input element relative to sMa
+  auto patch_meta = [&](int r, uint32_t x, uint32_t xs, uint32_t& src) -> uint32_t {
+    const uint32_t* nr = td.node[r < NODES ? r : r - NODES];
+    src = 0;
+    if (xs == NONE || xs >= nr[dN] || x < nr[dU0] || x >= nr[dU1]) return NONE;
+    src = nr[dSrel] + xs;
+    return (nr[dLi] << 16) | (nr[dD] + x);
+  };
+  // patch e's target (an insertion step's own slot) and source index loads;
+  // tl: a target entry (its range is NODES or above)
+  auto patch_fetch = [&](bool tl, int r, uint32_t e, uint32_t start, uint32_t& x, uint32_t& xs) {
     const uint64_t idx = (uint64_t)pbase[r] + (e - start);
-    const uint32_t u0 = nr[dU0], u1 = nr[dU1];
-    uint32_t x, xs;
-    if (r < NODES) {
-      x = max(u0, nr[dP]) + (e - start);
+    if (!tl) {
+      x = max(td.node[r][dU0], td.node[r][dP]) + (e - start);
       xs = a.tail_xsrc[idx];
     } else {
       x = a.pool_x[idx];
       xs = a.pool_xsrc[idx];
     }
-    meta = NONE;
-    if (xs == NONE || xs >= nr[dN] || x < u0 || x >= u1) return 0;
-    meta = (nr[dLi] << 16) | (nr[dD] + x);
-    return nr[dSrel] + xs;
   };
+  auto patch_at = [&](int rbeg, uint32_t e, uint32_t& meta) -> uint32_t {
+    uint32_t start, x, xs, src;
+    const int r = locate(rbeg, e, start);
+    patch_fetch(rbeg != 0, r, e, start, x, xs);
+    meta = patch_meta(r, x, xs, src);
+    return src;
+  };
+  // the first PK patches of each kind per thread, fetched ahead of the
+  // levels: every index load issued before any is used, then the values
   uint32_t pm[2 * PK];
   R pv[2 * PK];
+  {
+    uint32_t px[2 * PK], pxs[2 * PK];
+    int pr[2 * PK];
 #pragma unroll
-  for (int i = 0; i < PK; ++i) {
-    pm[i] = NONE;
-    pm[PK + i] = NONE;
-    const uint32_t e = tid + NT * i;
-    if (e < stot) {
-      const uint32_t src = patch_at(0, e, pm[i]);
-      if (pm[i] != NONE) pv[i] = reinterpret_cast<const R*>(XM)[src];
+    for (int i = 0; i < 2 * PK; ++i) {
+      const bool tl = i >= PK;
+      const uint32_t e = tid + NT * (uint32_t)(i % PK);
+      pr[i] = -1;
+      if (e < (tl ? ptot : stot)) {
+        uint32_t start;
+        pr[i] = locate(tl ? NODES : 0, e, start);
+        patch_fetch(tl, pr[i], e, start, px[i], pxs[i]);
+      }
     }
-    if (e < ptot) {
-      const uint32_t src = patch_at(NODES, e, pm[PK + i]);
-      if (pm[PK + i] != NONE) pv[PK + i] = reinterpret_cast<const R*>(XM)[src];
+#pragma unroll
+    for (int i = 0; i < 2 * PK; ++i) {
+      // every thread loads, element 0 of the merge when it has no patch (no
+      // branch around the load, so nothing waits for it before its use)
+      uint32_t src = 0;
+      pm[i] = NONE;
+      if (pr[i] >= 0) pm[i] = patch_meta(pr[i], px[i], pxs[i], src);
+      pv[i] = reinterpret_cast<const R*>(XM)[src];
     }
   }
   // the staged runs land in LDS
@@ -486,34 +514,41 @@ __device__ __forceinline__ void pass_body(const GroupArgs& a, uint32_t tile) {
     const uint32_t e0 = uniform_u32(td.dep_tb[LAM - 1 - li]);
     const uint32_t ne = uniform_u32(td.dep_tb[LAM - li]) - e0;
     if constexpr (sizeof(E) == 4) {
-      // groups of 8 slots (a quarter of a flip word): one entry read and one
-      // pair of counts per 8 slots
+      // groups of GS consecutive slots per thread (GPW groups to a flip
+      // word): one entry read and one pair of counts per group.  The lanes
+      // of a wave read A and B near 64 / GS * (lane) words apart, so fewer
+      // slots per group spread a read over more LDS banks.
+      constexpr uint32_t GS = kPassGroup4, GPW = 32u / GS;
       const uint32_t* src4 = reinterpret_cast<const uint32_t*>(src);
-      for (uint32_t q = tid; q < 4u * ne; q += NT) {
-        const uint2 t = td.tab[e0 + (q >> 2)];
-        const uint32_t G = 32u + 8u * q;
-        const uint32_t sh = 8u * (q & 3u);
+      for (uint32_t q = tid; q < GPW * ne; q += NT) {
+        const uint2 t = td.tab[e0 + q / GPW];
+        const uint32_t G = 32u + GS * q;
+        const uint32_t sh = GS * (q % GPW);
         const uint32_t lo = (1u << sh) - 1u;
         // byte offsets of the next A and B sources
         uint32_t za = 4u * ((t.y & 0xFFFFu) + (uint32_t)__popc(~t.x & lo));
         uint32_t ob = 4u * ((t.y >> 16) + (uint32_t)__popc(t.x & lo));
-        const uint32_t b8 = t.x >> sh;
+        const uint32_t bg = t.x >> sh;
         const char* srcb = reinterpret_cast<const char*>(src4);
-        uint32_t v[8];
+        uint32_t v[GS];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < (int)GS; ++j) {
           // all ones on a 1 flip: take B at ob, else A at za (the mask kept
           // opaque so that the choice stays one bit select)
-          uint32_t msk = (uint32_t)__builtin_amdgcn_sbfe((int)b8, (uint32_t)j, 1u);
+          uint32_t msk = (uint32_t)__builtin_amdgcn_sbfe((int)bg, (uint32_t)j, 1u);
           asm volatile("" : "+v"(msk));
           const uint32_t m4 = msk << 2;
           v[j] = *reinterpret_cast<const uint32_t*>(srcb + ((ob & msk) | (za & ~msk)));
           za += 4u + m4;
           ob -= m4;
         }
-        uint4* d4 = reinterpret_cast<uint4*>(&dst[G]);
-        d4[0] = make_uint4(v[0], v[1], v[2], v[3]);
-        d4[1] = make_uint4(v[4], v[5], v[6], v[7]);
+        if constexpr (GS == 2) {
+          *reinterpret_cast<uint2*>(&dst[G]) = make_uint2(v[0], v[1]);
+        } else {
+          uint4* d4 = reinterpret_cast<uint4*>(&dst[G]);
+#pragma unroll
+          for (int h = 0; h < (int)GS / 4; ++h) d4[h] = make_uint4(v[4 * h], v[4 * h + 1], v[4 * h + 2], v[4 * h + 3]);
+        }
       }
     } else
     for (uint32_t q = tid; q < 8u * ne; q += NT) {
