@@ -240,31 +240,57 @@ static uint64_t merge_r2(osrc *s, uint32_t *t, uint64_t n1, uint64_t n2,
     return P;
 }
 
-/* The in-place form of the printed listing: cursors u (output), v (head of
- * B), w (end).  A "take from B" swaps the head of A to where B's head was. */
+/* ------------------------------------------------------------------ */
+/* Algorithm 2 with the in-place placement of the appendix's merge     */
+/* (Appendix A.1): the coin-flip loop and the insertion loop are those */
+/* of Algorithm 2, only where the unplaced A elements sit differs.     */
+/* Working in place, A's unplaced elements occupy the slots between    */
+/* the output cursor and the head of B; a 1 flip moves B's head to the */
+/* output cursor and the A element it displaces to the end of that     */
+/* run.  So A's unplaced elements form a queue: a 0 flip places the    */
+/* queue's front, a 1 flip places B's next element and sends the       */
+/* queue's front to its back.  When B runs out the queue follows in    */
+/* queue order; when A runs out, the rest of B in its order.           */
+/* The queue is a circular buffer of A's indices.                      */
+/* ------------------------------------------------------------------ */
 static uint64_t merge_r1(osrc *s, uint32_t *t, uint64_t n1, uint64_t n2,
-                         uint32_t L, uint32_t m)
+                         uint32_t L, uint32_t m, uint32_t *tmp, uint32_t *queue)
 {
-    uint64_t n = n1 + n2, u = 0, v = n1, step = 0, P;
+    const uint32_t *A = t, *B = t + n1;
+    uint64_t n = n1 + n2, front = 0, len = n1, b = 0, k = 0, step = 0, P, i;
+    for (i = 0; i < n1; i++) queue[i] = (uint32_t)i;
     for (;;) {
-        int bit = random_bit(s, L, m, step);
+        int w = random_bit(s, L, m, step);
         step += 1;
-        if (bit) {
-            uint32_t x;
-            if (v == n) break;
-            x = t[u]; t[u] = t[v]; t[v] = x;
-            v += 1;
-        } else if (u == v) {
-            break;
+        if (w == 0) {
+            if (len == 0) break;
+            tmp[k++] = A[queue[front]];
+            front = front + 1 == n1 ? 0 : front + 1;
+            len -= 1;
+        } else {
+            if (b == n2) break;
+            tmp[k++] = B[b++];
+            if (len > 0) {
+                /* the front goes to the back: the slot after the last */
+                uint64_t back = front + len;
+                if (back >= n1) back -= n1;
+                queue[back] = queue[front];
+                front = front + 1 == n1 ? 0 : front + 1;
+            }
         }
-        u += 1;
     }
-    P = u;
-    while (u < n) {
-        uint64_t j = random_int(s, L, m, u, u + 1);
-        uint32_t x = t[j]; t[j] = t[u]; t[u] = x;
-        u += 1;
+    P = k;
+    while (len > 0) {
+        tmp[k++] = A[queue[front]];
+        front = front + 1 == n1 ? 0 : front + 1;
+        len -= 1;
     }
+    while (b < n2) tmp[k++] = B[b++];
+    for (i = P; i < n; i++) {
+        uint64_t j = random_int(s, L, m, i, i + 1);
+        uint32_t x = tmp[i]; tmp[i] = tmp[j]; tmp[j] = x;
+    }
+    memcpy(t, tmp, n * sizeof(uint32_t));
     return P;
 }
 
@@ -323,7 +349,12 @@ static uint64_t merge_balanced(osrc *s, uint32_t *t, uint64_t n1, uint64_t n2,
 }
 
 /* ------------------------------------------------------------------ */
-/* Algorithm MergeShuffle / Appendix A.2 shuffle().                    */
+/* Algorithm MergeShuffle: split into two halves, shuffle each, merge  */
+/* them (Algorithm 2); below the cutoff, Fisher-Yates (Algorithm 1).   */
+/* Unrolled bottom up: the recursion's leaves are the 2^c blocks of a  */
+/* c-level split, every level merging pairs of neighbouring blocks.    */
+/* Where each half ends is the reading of the partition of Appendix    */
+/* A.2: block i is [floor(n*i/2^c), floor(n*(i+1)/2^c)).               */
 /* ------------------------------------------------------------------ */
 static uint32_t levels_for(uint64_t n, uint64_t cutoff)
 {
@@ -342,23 +373,23 @@ static uint64_t run_shuffle(osrc *proto, uint32_t *t, uint64_t n, uint64_t cutof
 {
     uint32_t c, L;
     uint64_t q, i, bits = 0;
-    uint32_t *tmp = NULL;
+    uint32_t *tmp = NULL, *queue = NULL;
     uint8_t *word = NULL;
     (void)threads;
     if (n <= 1 || cutoff < 1) return 0;
     c = levels_for(n, cutoff);
     q = (uint64_t)1 << c;
-    if (placement == ORACLE_R2 || placement == ORACLE_BALANCED) {
-        tmp = (uint32_t *)malloc(n * sizeof(uint32_t));
-        if (!tmp) return ~(uint64_t)0;
-    }
+    tmp = (uint32_t *)malloc(n * sizeof(uint32_t));
+    if (!tmp) return ~(uint64_t)0;
     if (placement == ORACLE_BALANCED) {
         word = (uint8_t *)malloc(n);
         if (!word) { free(tmp); return ~(uint64_t)0; }
+    } else if (placement != ORACLE_R2) {
+        queue = (uint32_t *)malloc(n * sizeof(uint32_t));
+        if (!queue) { free(tmp); return ~(uint64_t)0; }
     }
 
-    /* leaves: one Fisher-Yates per block (parallel over blocks, as the
-     * listing's omp parallel for) */
+    /* leaves: one Fisher-Yates per block (the blocks are independent) */
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : bits) num_threads(threads > 0 ? threads : omp_get_max_threads()) if (!proto->script)
 #endif
@@ -388,12 +419,13 @@ static uint64_t run_shuffle(osrc *proto, uint32_t *t, uint64_t n, uint64_t cutof
             else if (placement == ORACLE_BALANCED)
                 merge_balanced(sp, t + j, k - j, l - k, L, (uint32_t)m, tmp + j, word + j);
             else
-                merge_r1(sp, t + j, k - j, l - k, L, (uint32_t)m);
+                merge_r1(sp, t + j, k - j, l - k, L, (uint32_t)m, tmp + j, queue + j);
             bits += s.bits;
         }
     }
     free(tmp);
     free(word);
+    free(queue);
     return bits;
 }
 
@@ -442,17 +474,19 @@ uint64_t oracle_merge_scripted(uint32_t *t, uint64_t n1, uint64_t n2, int placem
 {
     osrc s;
     uint64_t P;
-    uint32_t *tmp;
+    uint32_t *tmp, *queue;
     uint8_t *word;
     memset(&s, 0, sizeof s);
     s.script = script;
     s.script_len = script_len;
     tmp = (uint32_t *)malloc((n1 + n2 + 1) * sizeof(uint32_t));
+    queue = (uint32_t *)malloc((n1 + 1) * sizeof(uint32_t));
     word = (uint8_t *)malloc(n1 + n2 + 1);
     if (placement == ORACLE_R2) P = merge_r2(&s, t, n1, n2, 1, 0, tmp);
     else if (placement == ORACLE_BALANCED) P = merge_balanced(&s, t, n1, n2, 1, 0, tmp, word);
-    else P = merge_r1(&s, t, n1, n2, 1, 0);
+    else P = merge_r1(&s, t, n1, n2, 1, 0, tmp, queue);
     free(tmp);
+    free(queue);
     free(word);
     if (need) *need = s.starved ? s.need : 0;
     return s.starved ? ~(uint64_t)0 : P;
@@ -464,16 +498,18 @@ uint64_t oracle_merge_seeded(uint32_t *t, uint64_t n1, uint64_t n2, int placemen
 {
     osrc s;
     uint64_t P;
-    uint32_t *tmp;
+    uint32_t *tmp, *queue;
     uint8_t *word;
     memset(&s, 0, sizeof s);
     s.seed = seed;
     tmp = (uint32_t *)malloc((n1 + n2 + 1) * sizeof(uint32_t));
+    queue = (uint32_t *)malloc((n1 + 1) * sizeof(uint32_t));
     word = (uint8_t *)malloc(n1 + n2 + 1);
     if (placement == ORACLE_R2) P = merge_r2(&s, t, n1, n2, L, m, tmp);
     else if (placement == ORACLE_BALANCED) P = merge_balanced(&s, t, n1, n2, L, m, tmp, word);
-    else P = merge_r1(&s, t, n1, n2, L, m);
+    else P = merge_r1(&s, t, n1, n2, L, m, tmp, queue);
     free(tmp);
+    free(queue);
     free(word);
     if (bits) *bits += s.bits;
     return P;
