@@ -84,9 +84,37 @@ __device__ __forceinline__ void plan_count_body(const PlanArgs& pa, uint64_t chu
   pa.zloc[(chunk << kChunkGranLog) + threadIdx.x] = (uint16_t)ex;
   if (threadIdx.x == 0) pa.ctot[chunk] = total;
 }
+// The same, one wave per chunk (4 granules per lane, a wave scan, no
+// barrier), kCountChunksPerWave chunks per wave one after the other: a
+// workgroup per chunk spent more on starting workgroups than on the flips.
+constexpr uint32_t kCountChunksPerWave = 4;
 __global__ void __launch_bounds__(256) plan_count_kernel(PlanArgs pa) {
-  __shared__ uint32_t tmp[8];
-  plan_count_body(pa, blockIdx.x, tmp);
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t c0 = ((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kCountChunksPerWave;
+  const uint64_t c1 = min(c0 + kCountChunksPerWave, pa.total_chunks);
+  const Key key{pa.key0, pa.key1};
+  for (uint64_t chunk = c0; chunk < c1; ++chunk) {
+    const int l = level_of_chunk(pa, chunk);
+    const HbmLevel& lv = pa.lev[l];
+    const uint32_t rel = (uint32_t)(chunk - lv.chunk_base);
+    const uint32_t m = rel / lv.cpm;
+    const uint32_t ch = rel - m * lv.cpm;
+    const uint32_t g0 = (ch << kChunkGranLog) + 4u * lane;
+    uint32_t z[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const W4 f = flip_block(g0 + (uint32_t)e, m, lv.L, key);
+      z[e] = 128u - (uint32_t)(__popc(f.w[0]) + __popc(f.w[1]) + __popc(f.w[2]) + __popc(f.w[3]));
+    }
+    const uint32_t sum = z[0] + z[1] + z[2] + z[3];
+    const uint32_t incl = wave_incl_scan(sum);
+    const uint32_t ex = incl - sum;
+    // four 16-bit prefixes, as two 32-bit words
+    uint32_t* zl = reinterpret_cast<uint32_t*>(pa.zloc + (chunk << kChunkGranLog) + 4u * lane);
+    zl[0] = (ex & 0xFFFFu) | ((ex + z[0]) << 16);
+    zl[1] = ((ex + z[0] + z[1]) & 0xFFFFu) | ((ex + z[0] + z[1] + z[2]) << 16);
+    if (lane == 63) pa.ctot[chunk] = incl;
+  }
 }
 
 // Position (0..127) of the r-th zero (want_one = 0) or one (want_one = 1) of a block.
@@ -803,7 +831,8 @@ void launch_plan_multi(const PlanArgs* pas, uint32_t njobs, const uint32_t* cons
 
 void launch_plan(const PlanArgs& pa, hipStream_t st) {
   if (pa.nlev == 0) return;
-  hipLaunchKernelGGL(plan_count_kernel, dim3((uint32_t)pa.total_chunks), dim3(256), 0, st, pa);
+  const uint64_t count_wgs = (pa.total_chunks + 4 * kCountChunksPerWave - 1) / (4 * kCountChunksPerWave);
+  hipLaunchKernelGGL(plan_count_kernel, dim3((uint32_t)count_wgs), dim3(256), 0, st, pa);
   launch_scan(pa.ctot, pa.total_chunks, pa.part, pa.zg, ~0ull, pa.status, 0u, st);
   hipLaunchKernelGGL(zc_kernel, dim3((uint32_t)((std::max(pa.total_chunks, pa.total_buckets) + 255) / 256)), dim3(256),
                      0, st, pa);
