@@ -214,6 +214,9 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
     lv.tpm = (uint32_t)((nmax + T - 1) / T);
     const double ek = 0.8 * std::sqrt((double)nmax);
     lv.wpm = (uint32_t)std::max(1.0, std::ceil(ek / 1024.0));
+    // merges of at most about 256 insertion steps: one to a wave, four to a
+    // tail workgroup (most of a workgroup per merge would idle)
+    lv.mpw = ek <= 256.0 ? 4u : 1u;
     lv.chunk_base = chunks;
     lv.merge_base = merges;
     lv.bucket_base = buckets;
@@ -226,7 +229,7 @@ int make_plan(uint64_t n, uint32_t eb, const ms_config* cfg, HostPlan& hp) {
     chunks += (uint64_t)lv.nmerge * lv.cpm;
     merges += lv.nmerge;
     buckets += (uint64_t)lv.nmerge * lv.bpm;
-    wgs += (uint64_t)lv.nmerge * lv.wpm;
+    wgs += (uint64_t)(lv.nmerge + lv.mpw - 1) / lv.mpw * lv.wpm;
     cap += lcap;
     tiles = std::max<uint64_t>(tiles, (uint64_t)lv.nmerge * lv.tpm);
   }

@@ -295,10 +295,15 @@ __device__ __forceinline__ uint32_t tail_draw(const PlanArgs& pa, uint32_t L, ui
   return r.v;
 }
 
+// A tail workgroup's share of one merge: its part w of the merge's wpm parts,
+// worked by `lanes` threads (the workgroup, or one wave when the level puts
+// one merge on each wave); `act` is false for a wave past the level's last
+// merge (its k is 0 and it reads the last merge's fields).
 struct TailWg {
   const HbmLevel* lv;
   int l;
-  uint32_t m, w;
+  uint32_t m, w, lanes, lane;
+  bool act;
   MergeGeom g;
   uint32_t P, k;
   uint64_t gm, bb;
@@ -311,12 +316,23 @@ __device__ __forceinline__ TailWg tail_wg(const PlanArgs& pa, uint64_t wg) {
   t.lv = &pa.lev[l];
   // workgroups of one level number fewer than 2^32: a 32-bit division
   const uint32_t rel = (uint32_t)(wg - t.lv->wg_base);
-  t.m = rel / t.lv->wpm;
-  t.w = rel - t.m * t.lv->wpm;
+  if (t.lv->mpw > 1) {
+    t.m = rel * t.lv->mpw + (threadIdx.x >> 6);
+    t.w = 0;
+    t.lanes = 64;
+    t.lane = threadIdx.x & 63;
+  } else {
+    t.m = rel / t.lv->wpm;
+    t.w = rel - t.m * t.lv->wpm;
+    t.lanes = 256;
+    t.lane = threadIdx.x;
+  }
+  t.act = t.m < t.lv->nmerge;
+  if (!t.act) t.m = t.lv->nmerge - 1;
   t.g = merge_geom(pa, t.lv->L, t.m);
   t.gm = t.lv->merge_base + t.m;
   t.P = pa.P[t.gm];
-  t.k = t.g.N - t.P;
+  t.k = t.act ? t.g.N - t.P : 0u;
   t.bb = t.lv->bucket_base + (uint64_t)t.m * t.lv->bpm;
   return t;
 }
@@ -327,7 +343,7 @@ __device__ __forceinline__ TailWg tail_wg(const PlanArgs& pa, uint64_t wg) {
 __device__ __forceinline__ void tail_count_body(const PlanArgs& pa, uint64_t wg, uint64_t* red) {
   const TailWg t = tail_wg(pa, wg);
   uint32_t bits = 0;
-  for (uint32_t d = t.w * 256 + threadIdx.x; d < t.k; d += t.lv->wpm * 256) {
+  for (uint32_t d = t.w * t.lanes + t.lane; d < t.k; d += t.lv->wpm * t.lanes) {
     const uint32_t i = t.P + d;
     const uint32_t j = tail_draw(pa, t.lv->L, t.m, i, &bits);
     if (j != i) atomicAdd(&pa.bcnt[t.bb + (j >> t.lv->blog)], 1u);
@@ -463,7 +479,7 @@ __device__ __forceinline__ void tail_scatter_body(const PlanArgs& pa, uint64_t w
   }
   const TailWg t = tail_wg(pa, wg);
   uint32_t bits = 0;
-  for (uint32_t d = t.w * 256 + threadIdx.x; d < t.k; d += t.lv->wpm * 256) {
+  for (uint32_t d = t.w * t.lanes + t.lane; d < t.k; d += t.lv->wpm * t.lanes) {
     const uint32_t i = t.P + d;
     const uint32_t j = tail_draw(pa, t.lv->L, t.m, i, &bits);
     if (j == i) continue;
@@ -562,7 +578,7 @@ __device__ __forceinline__ void tail_resolve_body(const PlanArgs& pa, uint64_t w
   const uint32_t side = pa.side[t.gm];
   const uint64_t toff = pa.toff[t.gm];
   // slots P..N-1, one per step
-  for (uint32_t d = t.w * 256 + threadIdx.x; d < t.k; d += lv.wpm * 256) {
+  for (uint32_t d = t.w * t.lanes + t.lane; d < t.k; d += lv.wpm * t.lanes) {
     const uint32_t x = t.P + d;
     uint32_t out = kNone32;
     if (max_target(pa, t.bb, lv.blog, x, kNone32) == kNone32) {
@@ -589,9 +605,9 @@ __device__ __forceinline__ void tail_resolve_body(const PlanArgs& pa, uint64_t w
   }
   // target entries: final if theirs is the last step targeting the slot
   const uint64_t lo = pa.boff[t.bb];
-  uint64_t hi = pa.boff[t.bb + lv.bpm];
+  uint64_t hi = t.act ? pa.boff[t.bb + lv.bpm] : lo;
   if (hi > pa.pool_cap) hi = pa.pool_cap;
-  for (uint64_t e = lo + (uint64_t)t.w * 256 + threadIdx.x; e < hi; e += (uint64_t)lv.wpm * 256) {
+  for (uint64_t e = lo + (uint64_t)t.w * t.lanes + t.lane; e < hi; e += (uint64_t)lv.wpm * t.lanes) {
     const uint32_t x = pa.pool_x[e];
     const uint32_t st = pa.pool_step[e];
     uint32_t out = kNone32;
@@ -647,14 +663,14 @@ __device__ __forceinline__ void trace_body(const PlanArgs& pa, uint64_t wg) {
   const TailWg t = tail_wg(pa, wg);
   const int l = t.l;
   const uint64_t toff = pa.toff[t.gm];
-  for (uint32_t d = t.w * 256 + threadIdx.x; d < t.k; d += t.lv->wpm * 256) {
+  for (uint32_t d = t.w * t.lanes + t.lane; d < t.k; d += t.lv->wpm * t.lanes) {
     if (toff + d >= pa.tail_cap) break;
     pa.tail_xsrc[toff + d] = trace_to_input(pa, l, t.m, pa.tail_src[toff + d]);
   }
   const uint64_t lo = pa.boff[t.bb];
-  uint64_t hi = pa.boff[t.bb + t.lv->bpm];
+  uint64_t hi = t.act ? pa.boff[t.bb + t.lv->bpm] : lo;
   if (hi > pa.pool_cap) hi = pa.pool_cap;
-  for (uint64_t e = lo + (uint64_t)t.w * 256 + threadIdx.x; e < hi; e += (uint64_t)t.lv->wpm * 256)
+  for (uint64_t e = lo + (uint64_t)t.w * t.lanes + t.lane; e < hi; e += (uint64_t)t.lv->wpm * t.lanes)
     pa.pool_xsrc[e] = trace_to_input(pa, l, t.m, pa.pool_src[e]);
 }
 

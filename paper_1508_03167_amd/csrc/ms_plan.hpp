@@ -37,7 +37,7 @@ struct HbmLevel {
   uint32_t blog;          // target-entry buckets of 2^blog slots (about 2.5 sqrt(N): ~1.6 entries each)
   uint32_t grp;           // fused pass this level belongs to
   uint32_t gli;           // its index within the pass, 0 = the level reading the pass input
-  uint32_t pad;
+  uint32_t mpw;           // merges per tail workgroup: 4 (one to a wave) for small merges, else 1
   uint64_t chunk_base;    // first chunk of this level (ctot, zc); granules at chunk_base << 8
   uint64_t merge_base;    // first merge of this level in the per-merge arrays
   uint64_t bucket_base;   // first bucket of this level
