@@ -525,9 +525,11 @@ __device__ __forceinline__ void pass_body(const GroupArgs& a, uint32_t tile) {
         const uint32_t G = 32u + GS * q;
         const uint32_t sh = GS * (q % GPW);
         const uint32_t lo = (1u << sh) - 1u;
-        // byte offsets of the next A and B sources
-        uint32_t za = 4u * ((t.y & 0xFFFFu) + (uint32_t)__popc(~t.x & lo));
-        uint32_t ob = 4u * ((t.y >> 16) + (uint32_t)__popc(t.x & lo));
+        // byte offsets of the next A and B sources (the zeros before the
+        // group are its offset in the word less the ones)
+        const uint32_t ones = (uint32_t)__popc(t.x & lo);
+        uint32_t za = 4u * ((t.y & 0xFFFFu) + sh - ones);
+        uint32_t ob = 4u * ((t.y >> 16) + ones);
         const uint32_t bg = t.x >> sh;
         const char* srcb = reinterpret_cast<const char*>(src4);
         uint32_t v[GS];
