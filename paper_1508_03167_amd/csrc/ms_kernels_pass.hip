@@ -92,6 +92,22 @@ enum {
   kU0, kU1, kRa0, kRa1, kP, kSide, kM, kL, kTb, kD, kBlk, kZf, kToff, kN, kLi, kRes, kNF
 };
 
+// Entry li (< LAM, different per lane) of a per-level argument array: a
+// select over the LAM entries, which stay scalar, rather than a vector load
+// from the argument memory with its own wait.
+__device__ __forceinline__ uint32_t scalar_of(uint32_t v) { return uniform_u32(v); }
+__device__ __forceinline__ uint64_t scalar_of(uint64_t v) { return uniform_u64((uint32_t)(v >> 32), (uint32_t)v); }
+template <int LAM, typename T>
+__device__ __forceinline__ T level_pick(const T (&v)[kGroupMax], int li) {
+  T x = scalar_of(v[0]);
+#pragma unroll
+  for (int i = 1; i < LAM; ++i) {
+    const T y = scalar_of(v[i]);
+    x = li == i ? y : x;
+  }
+  return x;
+}
+
 // The descriptor of one tile (tile = top merge * tpm + tile within it), by
 // NTB threads, into global memory at out.
 template <typename E, int T, int LAM, int NTB>
@@ -124,7 +140,7 @@ __device__ __forceinline__ void desc_body(const GroupArgs& a, uint32_t tile, uin
     const int d = 31 - __clz(k + 1);
     const int li = LAM - 1 - d;
     const uint32_t m = (M << d) + (uint32_t)(k - ((1 << d) - 1));
-    const uint64_t gm = a.merge_base[li] + m;
+    const uint64_t gm = level_pick<LAM>(a.merge_base, li) + m;
     nd[k][kP] = a.P[gm];
     nd[k][kSide] = a.side[gm];
     nd[k][kToff] = a.toff[gm];
@@ -139,7 +155,10 @@ __device__ __forceinline__ void desc_body(const GroupArgs& a, uint32_t tile, uin
   // 2. the window tree, one lane of wave 0 per window: table entries and
   //    flip blocks by prefix over the windows (breadth first, so each
   //    level's windows are consecutive), positions, staged runs, and the
-  //    insertion-loop ranges
+  //    insertion-loop ranges (their bucket offsets are loaded here and used
+  //    after the table is built, so the loads overlap the flips)
+  uint64_t p_lo = 0, p_hi = 0;
+  bool p_any = false;
   if (tid < 64) {
     const int k = tid;
     const bool act = k < NODES;
@@ -154,7 +173,7 @@ __device__ __forceinline__ void desc_body(const GroupArgs& a, uint32_t tile, uin
       ra0 = rec[0][2 * k + 1];
       ra1 = rec[1][2 * k + 1];
       m = (M << d) + idx;
-      L = a.L[li];
+      L = level_pick<LAM>(a.L, li);
       const uint64_t i0 = (uint64_t)m << L;
       s0 = bound(a.n, i0, a.c);
       const uint64_t mid = bound(a.n, i0 + (1ull << (L - 1)), a.c);
@@ -228,13 +247,12 @@ __device__ __forceinline__ void desc_body(const GroupArgs& a, uint32_t tile, uin
       uint32_t sc = x1 - x0;
       if (sb >= a.tail_cap) sc = 0;
       else if (sb + sc > a.tail_cap) sc = (uint32_t)(a.tail_cap - sb);
-      uint32_t plo = 0, pc = 0;
       if (u1 > u0) {
-        const uint64_t bb = a.bucket_base[li] + (uint64_t)m * a.bpm[li];
-        const uint64_t lo = a.boff[bb + (u0 >> a.blog[li])];
-        const uint64_t hi = min((uint64_t)a.boff[bb + ((u1 - 1) >> a.blog[li]) + 1], a.pool_cap);
-        plo = (uint32_t)lo;
-        pc = hi > lo ? (uint32_t)(hi - lo) : 0u;
+        const uint64_t bb = level_pick<LAM>(a.bucket_base, li) + (uint64_t)m * level_pick<LAM>(a.bpm, li);
+        const uint32_t blg = level_pick<LAM>(a.blog, li);
+        p_lo = a.boff[bb + (u0 >> blg)];
+        p_hi = a.boff[bb + ((u1 - 1) >> blg) + 1];
+        p_any = true;
       }
       uint32_t* r = td.node[k];
       r[dU0] = u0;
@@ -246,8 +264,6 @@ __device__ __forceinline__ void desc_body(const GroupArgs& a, uint32_t tile, uin
       r[dSrel] = (uint32_t)(s0 - sMa);
       r[dDbase] = (uint32_t)sb;
       r[dDcnt] = sc;
-      r[dPlo] = plo;
-      r[dPcnt] = pc;
       r[dPad] = 0u;
       if (k == 0) {
         td.len = u1 - u0;
@@ -328,6 +344,13 @@ __device__ __forceinline__ void desc_body(const GroupArgs& a, uint32_t tile, uin
       const uint32_t za = c.y + z, ob = c.z + 32u * w - z;
       td.tab[e].y = (za & 0xFFFFu) | (ob << 16);
     }
+  }
+  __syncthreads();
+  // the windows' target-entry ranges, from the loads issued in step 2
+  if (tid < NODES) {
+    const uint64_t hi = min(p_hi, a.pool_cap);
+    td.node[tid][dPlo] = p_any ? (uint32_t)p_lo : 0u;
+    td.node[tid][dPcnt] = p_any && hi > p_lo ? (uint32_t)(hi - p_lo) : 0u;
   }
   __syncthreads();
   // 6. out
