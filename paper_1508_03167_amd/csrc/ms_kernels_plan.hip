@@ -549,24 +549,36 @@ __device__ __forceinline__ uint32_t r1_a_source(const PlanArgs& pa, const HbmLev
   return q;
 }
 
-// Merge-relative input offset of C0[src] (the array before the insertion loop).
-__device__ __forceinline__ uint32_t c0_offset(const PlanArgs& pa, const HbmLevel& lv, uint32_t m,
-                                              const MergeGeom& g, uint32_t P, uint32_t side, uint32_t src) {
+// Merge-relative input offset of C0[src] (the array before the insertion
+// loop); z0 = zeros of the merge before src's granule when src < P.
+__device__ __forceinline__ uint32_t c0_offset_z(const PlanArgs& pa, const HbmLevel& lv, uint32_t m,
+                                                const MergeGeom& g, uint32_t P, uint32_t side, uint32_t src,
+                                                uint32_t z0) {
   if (src >= P) {
     if (side == 0) return src;
     return pa.placement ? r1_a_source(pa, lv, m, g.n1, src) : src - g.n2;
   }
-  const uint64_t cglob = lv.chunk_base + (uint64_t)m * lv.cpm + (src >> kChunkLog);
   const uint32_t gi = src >> kGranLog;
   const W4 f = flip_block(gi, m, lv.L, Key{pa.key0, pa.key1});
   const uint32_t wsel = (src >> 5) & 3;
-  uint32_t z = pa.zc[cglob] + pa.zloc[(cglob << kChunkGranLog) + (gi & 255)];
+  uint32_t z = z0;
   for (uint32_t w = 0; w < wsel; ++w) z += 32u - (uint32_t)__popc(f.w[w]);
   const uint32_t word = pick(f, wsel);
   const uint32_t bit = src & 31;
   z += (uint32_t)__popc(~word & ((1u << bit) - 1u));
   if ((word >> bit) & 1u) return g.n1 + (src - z);
   return pa.placement ? r1_a_source(pa, lv, m, g.n1, src) : z;
+}
+
+// The same, reading the granule's zero count from the plan tables.
+__device__ __forceinline__ uint32_t c0_offset(const PlanArgs& pa, const HbmLevel& lv, uint32_t m,
+                                              const MergeGeom& g, uint32_t P, uint32_t side, uint32_t src) {
+  uint32_t z0 = 0;
+  if (src < P) {
+    const uint64_t cglob = lv.chunk_base + (uint64_t)m * lv.cpm + (src >> kChunkLog);
+    z0 = pa.zc[cglob] + pa.zloc[(cglob << kChunkGranLog) + ((src >> kGranLog) & 255)];
+  }
+  return c0_offset_z(pa, lv, m, g, P, side, src, z0);
 }
 
 // ---------------------------------------------------------------------------
@@ -625,23 +637,30 @@ __global__ void __launch_bounds__(256) tail_resolve_kernel(PlanArgs pa) { tail_r
 // ---------------------------------------------------------------------------
 // The source of slot pos's final value at level lev[l], merge m, as an offset
 // into the output of the level below (relative to the merge's first element).
+// (every table read the three cases may need is issued first, together:
+// the merge's break and side, pos's bucket range and granule counts; then
+// the bucket's first entries and pos's tail slot)
 __device__ __forceinline__ uint32_t final_source(const PlanArgs& pa, int l, uint32_t m, uint32_t pos) {
   const HbmLevel& lv = pa.lev[l];
   const uint64_t gm = lv.merge_base + m;
   const MergeGeom g = merge_geom(pa, lv.L, m);
+  const uint64_t b = lv.bucket_base + (uint64_t)m * lv.bpm + (pos >> lv.blog);
+  const uint64_t cglob = lv.chunk_base + (uint64_t)m * lv.cpm + (pos >> kChunkLog);
   const uint32_t P = pa.P[gm];
-  const uint64_t bb = lv.bucket_base + (uint64_t)m * lv.bpm;
-  const uint64_t b = bb + (pos >> lv.blog);
+  const uint32_t side = pa.side[gm];
+  const uint64_t toff = pa.toff[gm];
   const uint64_t lo = pa.boff[b];
-  uint64_t hi = lo + pa.bcnt[b];
+  const uint32_t cnt = pa.bcnt[b];
+  const uint32_t z0 = pa.zc[cglob] + pa.zloc[(cglob << kChunkGranLog) + ((pos >> kGranLog) & 255)];
+  uint64_t hi = lo + cnt;
   if (hi > pa.pool_cap) hi = pa.pool_cap;
   for (uint64_t e = lo; e < hi; ++e)
     if (pa.pool_x[e] == pos && pa.pool_src[e] != kNone32) return pa.pool_src[e];
   if (pos >= P) {
-    const uint64_t t = (uint64_t)pa.toff[gm] + (pos - P);
+    const uint64_t t = toff + (pos - P);
     if (t < pa.tail_cap && pa.tail_src[t] != kNone32) return pa.tail_src[t];
   }
-  return c0_offset(pa, lv, m, g, P, pa.side[gm], pos);
+  return c0_offset_z(pa, lv, m, g, P, side, pos, z0);
 }
 
 __device__ __forceinline__ uint32_t trace_to_input(const PlanArgs& pa, int l, uint32_t m, uint32_t off) {
