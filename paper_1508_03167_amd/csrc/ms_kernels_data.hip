@@ -554,7 +554,12 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
   constexpr int SPT = SCAP / NT + 1;                              // slots of a leaf per thread, at most
   constexpr int MAXV = (int)((SCAP * sizeof(E) / 16 + NT - 1) / NT);  // 16-byte groups per thread
   static_assert(SCAP * sizeof(E) >= 4 * SCAP, "list heads and links live in the data region");
-  __shared__ __align__(16) E data[SCAP + 1];  // one spare element: the word straight loops write to
+  // past the super-block's slots: 64 spare words, one per lane of a wave,
+  // that the straight-line loops address for slots and steps that do not
+  // exist (one shared spare word would take all those lanes' writes at one
+  // address in one instruction)
+  constexpr int kSpare = (int)(256 / sizeof(E));
+  __shared__ __align__(16) E data[SCAP + kSpare];
   __shared__ MergeAux<SCAP> maux;
   __shared__ uint32_t tmp[20];
   __shared__ uint32_t mP[kLeafMaxMerges];
@@ -580,9 +585,9 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
   const uint32_t b = (uint32_t)(bound(a.n, u + 1, a.c) - bound(a.n, u, a.c));
   uint16_t* head = reinterpret_cast<uint16_t*>(data);
   uint32_t F[(SPT + 1) / 2];
-  // the spare word past the super-block's slots (lists use one word per slot)
-  constexpr uint32_t kDummy = SCAP * sizeof(E) / 4;
-  leaf_fy_sources<BPT, SPT, NT>(head, lb, b, kDummy, (uint32_t)u, lt, tpl, key, &bits, a.status, F);
+  // this lane's spare word (lists use one word per slot)
+  const uint32_t dummy = (uint32_t)(SCAP * sizeof(E) / 4) + (uint32_t)(tid & 63);
+  leaf_fy_sources<BPT, SPT, NT>(head, lb, b, dummy, (uint32_t)u, lt, tpl, key, &bits, a.status, F);
   (void)nleaf;
 
   if (IDENT) {
