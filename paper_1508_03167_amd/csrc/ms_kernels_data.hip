@@ -600,12 +600,14 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, const uint64_t sb) 
     using R = typename RegOf<E>::type;
     R* dataR = reinterpret_cast<R*>(data);
     R val[SPT];
-    // (a slot that does not exist has source 0 and writes the spare element)
-    for_slots<SPT>(lt, tpl, lb, b, SCAP, [&](int i, uint32_t, uint32_t, bool) {
+    // (a slot that does not exist has source 0 and writes the lane's spare
+    // element)
+    const uint32_t spare = SCAP + (uint32_t)(tid % kSpare);
+    for_slots<SPT>(lt, tpl, lb, b, spare, [&](int i, uint32_t, uint32_t, bool) {
       val[i] = dataR[lb + get16(F[i >> 1], i & 1)];
     });
     __syncthreads();
-    for_slots<SPT>(lt, tpl, lb, b, SCAP, [&](int i, uint32_t, uint32_t w, bool) { dataR[w] = val[i]; });
+    for_slots<SPT>(lt, tpl, lb, b, spare, [&](int i, uint32_t, uint32_t w, bool) { dataR[w] = val[i]; });
     __syncthreads();
   }
 
