@@ -359,10 +359,10 @@ __device__ __forceinline__ void desc_body(const GroupArgs& a, uint32_t tile, uin
   for (uint32_t i = tid; i < DW4; i += NTB) dst[i] = src[i];
 }
 
-// One tile of one fused pass, from its descriptor.
 // slots per thread and step in the 4-byte levels
 constexpr uint32_t kPassGroup4 = 4;
 
+// One tile of one fused pass, from its descriptor.
 template <typename E, int T, int LAM, int NT>
 __device__ __forceinline__ void pass_body(const GroupArgs& a, uint32_t tile) {
   using S = DescShape<T, LAM>;
