@@ -4,6 +4,8 @@ The oracle's results at these sizes are stored in tests/golden/configs.json
 (written by tests/golden/make_golden.py from the oracle alone): the random-bit
 count, two order-sensitive fingerprints of the whole permutation and 512
 sampled slots.  The GPU side computes the same fingerprints on the device.
+The benchmark workload itself (n = 2^30, seed 7) is also compared element by
+element with the oracle run on the host.
 """
 import json
 import os
@@ -56,6 +58,29 @@ def test_permutation_n2p30_seed7(M):
     del out, x
     M.release()
     torch.cuda.empty_cache()
+
+
+def test_permutation_n2p30_seed7_every_element(M):
+    # the benchmark workload compared element by element with the oracle run
+    # on the host's cores (about 20 s at 16 threads)
+    import torch
+
+    from oracle import oracle as O
+
+    n, seed = 1 << 30, 7
+    print(f"[gpu] full-size permutation n={n} seed={seed}, every element", flush=True)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    bits = torch.zeros(1, dtype=torch.int64, device="cuda")
+    M.permutation(out, seed, bits=bits)
+    torch.cuda.synchronize()
+    assert M.device_status() == 0
+    got = out.cpu().numpy().view(np.uint32)
+    del out
+    M.release()
+    torch.cuda.empty_cache()
+    want, want_bits = O.permutation(n, 4096, seed, threads=O.max_threads())
+    assert int(bits.item()) == want_bits
+    assert np.array_equal(got, want)
 
 
 def test_permutation_largest_accepted_size(M):
