@@ -135,6 +135,11 @@ def test_records16_n2p27_seed11(M):
     pos = torch.tensor([p for p, _ in g["samples"]], dtype=torch.int64, device="cuda")
     assert payload[pos].cpu().numpy().tolist() == [v for _, v in g["samples"]]
     assert torch.equal(rec[:, 0], keys0[payload])
+    # every record: the payloads are the oracle's permutation of 0..n-1
+    from oracle import oracle as O
+
+    want, _ = O.permutation(g["n"], 4096, g["seed"], threads=O.max_threads())
+    assert np.array_equal(payload.cpu().numpy(), want.astype(np.int64))
     del rec, keys0, payload
     M.release()
     torch.cuda.empty_cache()
