@@ -309,7 +309,8 @@ def plan(n: int, elem_bytes: int = 4, leaf_B=0, lds_levels_max=0, hbm_only=False
 
 def device_status(stream=None) -> int:
     """Synchronize the stream, then read and clear the status flags of the
-    calls made on it and of the allocation-free entry point (0 = clean).  Raises MSError if the synchronization or the read fails."""
+    calls made on it and of the allocation-free entry point (0 = clean).
+    Raises MSError if the synchronization or the read fails."""
     flags = ctypes.c_uint32(0)
     rc = lib().ms_device_status(_stream(stream), ctypes.byref(flags))
     if rc not in (MS_OK, MS_ERR_CAPACITY):
