@@ -83,6 +83,52 @@ def test_permutation_n2p30_seed7_every_element(M):
     assert np.array_equal(got, want)
 
 
+def test_ragged_n_near_2p30_every_element(M):
+    # n = 2^30 - 12345: leaves of 4095 and 4096 elements, every merge and
+    # tile of the fused passes ragged
+    import torch
+
+    from oracle import oracle as O
+
+    n, seed = (1 << 30) - 12345, 21
+    print(f"[gpu] ragged permutation n={n} seed={seed}, every element", flush=True)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    bits = torch.zeros(1, dtype=torch.int64, device="cuda")
+    M.permutation(out, seed, bits=bits)
+    torch.cuda.synchronize()
+    assert M.device_status() == 0
+    got = out.cpu().numpy().view(np.uint32)
+    del out
+    M.release()
+    torch.cuda.empty_cache()
+    want, want_bits = O.permutation(n, 4096, seed, threads=O.max_threads())
+    assert int(bits.item()) == want_bits
+    assert np.array_equal(got, want)
+
+
+def test_records8_n2p28_every_element(M):
+    # 8-byte elements at scale: x[i] = i as uint64, shuffled in place, equals
+    # the oracle's permutation of 0..n-1
+    import torch
+
+    from oracle import oracle as O
+
+    n, seed = (1 << 28) + 7, 13
+    print(f"[gpu] 8-byte shuffle n={n} seed={seed}, every element", flush=True)
+    x = torch.arange(n, dtype=torch.int64, device="cuda")
+    bits = torch.zeros(1, dtype=torch.int64, device="cuda")
+    M.shuffle_(x, seed, bits=bits)
+    torch.cuda.synchronize()
+    assert M.device_status() == 0
+    got = x.cpu().numpy()
+    del x
+    M.release()
+    torch.cuda.empty_cache()
+    want, want_bits = O.permutation(n, 4096, seed, threads=O.max_threads())
+    assert int(bits.item()) == want_bits
+    assert np.array_equal(got, want.astype(np.int64))
+
+
 def test_permutation_largest_accepted_size(M):
     # n = 2^32 - 2^16, the largest n the library accepts: slot indices use all
     # 32 bits, the top merge spans the whole array
