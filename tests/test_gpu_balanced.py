@@ -49,6 +49,23 @@ def test_permutation_equals_the_oracle(M, n, B, seed):
     assert int(bits.item()) == wbits
 
 
+def test_bench_size_balanced(M):
+    # the size and seed bench.py times BalancedShuffle at
+    import torch
+
+    n, seed = 1 << 26, 7
+    print(f"[gpu] balanced n={n} seed={seed}", flush=True)
+    want = np.arange(n, dtype=np.uint32)
+    wbits = O.shuffle_u32(want, 4096, seed, O.BALANCED, threads=O.max_threads())
+    x = torch.empty(n, dtype=torch.int32, device="cuda")
+    bits = torch.zeros(1, dtype=torch.int64, device="cuda")
+    M.permutation(x, seed, bits=bits, placement="BAL")
+    torch.cuda.synchronize()
+    assert M.device_status() == 0
+    assert np.array_equal(x.cpu().numpy().view(np.uint32), want)
+    assert int(bits.item()) == wbits
+
+
 @pytest.mark.parametrize("eb", [8, 16])
 def test_records_move_with_the_permutation(M, eb):
     import torch

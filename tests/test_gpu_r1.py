@@ -53,6 +53,22 @@ def test_permutation_matches_oracle_r1(M, n):
     assert int(bits.item()) == wbits
 
 
+def test_bench_size_r1(M):
+    # the size and seed bench.py times the listing placement at
+    import torch
+
+    n, seed = 1 << 26, 7
+    _say(f"[gpu] r1 permutation n={n} seed={seed}")
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    bits = torch.zeros(1, dtype=torch.int64, device="cuda")
+    M.permutation(out, seed, bits=bits, placement="R1")
+    torch.cuda.synchronize()
+    assert M.device_status() == 0
+    want, wbits = _oracle_r1(n, 4096, seed)
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), want)
+    assert int(bits.item()) == wbits
+
+
 def test_same_bits_as_stable_interleave_but_another_permutation(M):
     import torch
 
