@@ -89,6 +89,48 @@ def test_log_uniform_sizes(M):
     _check(M, sizes, [4] * len(sizes), 3)
 
 
+def test_batched_workload_at_full_size(M):
+    # the batched workload bench.py times: 4096 uint32 identity arrays, sizes
+    # floor(2^(8 + 12u)) from seed 3, array a shuffled with seed 3 + a; the
+    # eager call, then one replay of its captured graph on fresh arrays,
+    # every array against the oracle
+    import torch
+
+    from paper_1508_03167_amd import inputs
+
+    sizes = [int(x) for x in inputs.batched_sizes(4096, 3)]
+    seeds = [3 + a for a in range(len(sizes))]
+    _say(f"[gpu] batched workload: {len(sizes)} arrays, {sum(sizes)} elements")
+    dev = [torch.arange(n, dtype=torch.int32, device="cuda") for n in sizes]
+    bits = torch.zeros(len(sizes), dtype=torch.int64, device="cuda")
+    M.shuffle_batched_(dev, 3, bits=bits)
+    torch.cuda.synchronize()
+    assert M.device_status() == 0
+    got_bits = bits.cpu().numpy()
+    wants, wbitss = [], []
+    for a, n in enumerate(sizes):
+        want, wbits = O.permutation(n, 4096, seeds[a], threads=O.max_threads())
+        assert np.array_equal(dev[a].cpu().numpy().view(np.uint32), want), (a, n)
+        assert got_bits[a] == wbits, (a, n)
+        wants.append(want)
+        wbitss.append(wbits)
+    for a, n in enumerate(sizes):
+        dev[a].copy_(torch.arange(n, dtype=torch.int32, device="cuda"))
+    bits.zero_()
+    torch.cuda.synchronize()
+    with M.BatchGraph(dev, seeds, bits=bits) as g:
+        g.launch()
+        assert g.status() == 0
+        torch.cuda.synchronize()
+    got_bits = bits.cpu().numpy()
+    for a, n in enumerate(sizes):
+        assert np.array_equal(dev[a].cpu().numpy().view(np.uint32), wants[a]), ("graph", a, n)
+        assert got_bits[a] == wbitss[a], ("graph", a, n)
+    del dev
+    M.release()
+    torch.cuda.empty_cache()
+
+
 def test_batched_equals_one_call_per_array(M):
     import torch
 
